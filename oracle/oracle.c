@@ -1,0 +1,482 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the limited lattice Boltzmann step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Sequential loops in row-major
+ * node order, no blocking or fusion: each function follows one formula of
+ * Brownlee, Gorban & Levesley (arXiv:0704.0043) so that it can be checked
+ * against the paper by eye.  Built with -O2 -ffp-contract=off.
+ *
+ * Readings of points where the paper is silent or garbled:
+ *   - D1Q3 entropic f*: the printed left/right movers contradict the velocity
+ *     labels of Sec. 4.1; the mover with velocity v = +-1 is taken as
+ *     (rho/6)(+-3u - 1 + 2 sqrt(1+3u^2)), the 1-D factor of eq. (maxwellian).
+ *   - Quadratic Delta S carries the factor 1/2 of the Taylor expansion
+ *     (Sec. 3.6 prints it without).
+ *   - The limiter acts on the post-collision state f' (Sec. 4.3.2: the limiter
+ *     is a post-processing step immediately after collision).
+ *   - Non-positive populations make the logarithm undefined: Delta S = +inf,
+ *     so every enabled limiter returns the site to f*.
+ *   - Free flight off the edge of a non-periodic grid is reflected into the
+ *     same node's opposite population (half-way bounce-back at the tube ends;
+ *     at cavity wall nodes it only touches populations that never reach the
+ *     fluid).  With this rule free flight is a permutation.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- lattices (Sec. 4.1) ------------------------------------------------ */
+
+/* D1Q3: static, left-moving (v = -1), right-moving (v = +1) in the paper's
+ * order f1, f2, f3 (0-based here).  Entropy weights from
+ * H = f1 log(f1/4) + f2 log f2 + f3 log f3. */
+static const int D1_VX[3] = {0, -1, 1};
+static const int D1_OPP[3] = {0, 2, 1};
+static const double D1_W[3] = {4.0, 1.0, 1.0};
+
+/* D2Q9: rest, E, N, W, S, NE, NW, SW, SE with weights 4/9, 1/9, 1/36. */
+static const int D2_VX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int D2_VY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int D2_OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double D2_W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                               1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+int orc_q(int32_t lattice)
+{
+    if (lattice == ORC_D1Q3) return 3;
+    if (lattice == ORC_D2Q9) return 9;
+    return 0;
+}
+
+void orc_velocity(int32_t lattice, int32_t i, int32_t* vx, int32_t* vy)
+{
+    if (lattice == ORC_D1Q3) {
+        *vx = D1_VX[i];
+        *vy = 0;
+    } else {
+        *vx = D2_VX[i];
+        *vy = D2_VY[i];
+    }
+}
+
+int orc_opposite(int32_t lattice, int32_t i)
+{
+    return lattice == ORC_D1Q3 ? D1_OPP[i] : D2_OPP[i];
+}
+
+/* ---- quasiequilibria (Sec. 4.1) ----------------------------------------- */
+
+void orc_equilibrium(int32_t lattice, int32_t qe, double rho, double ux,
+                     double uy, double* fstar)
+{
+    if (lattice == ORC_D1Q3) {
+        double u = ux;
+        if (qe == ORC_QE_POLY) {
+            /* eq. (polyeq1d) */
+            fstar[0] = 2.0 * rho / 3.0 * (1.0 - 3.0 * u * u / 2.0);
+            fstar[1] = rho / 6.0 * (1.0 - 3.0 * u + 3.0 * u * u);
+            fstar[2] = rho / 6.0 * (1.0 + 3.0 * u + 3.0 * u * u);
+        } else {
+            /* eq. (entropiceq1d), movers assigned by their velocity */
+            double s = sqrt(1.0 + 3.0 * u * u);
+            fstar[0] = 2.0 * rho / 3.0 * (2.0 - s);
+            fstar[1] = rho / 6.0 * (-3.0 * u - 1.0 + 2.0 * s);
+            fstar[2] = rho / 6.0 * (3.0 * u - 1.0 + 2.0 * s);
+        }
+        return;
+    }
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; ++i) {
+        if (qe == ORC_QE_POLY) {
+            /* eq. (polyeq2d) */
+            double cu = D2_VX[i] * ux + D2_VY[i] * uy;
+            fstar[i] = rho * D2_W[i] *
+                       (1.0 + 3.0 * cu + 9.0 * cu * cu / 2.0 - 3.0 * uu / 2.0);
+        } else {
+            /* eq. (maxwellian): product over the two axes */
+            double prod = 1.0;
+            double u[2] = {ux, uy};
+            int v[2] = {D2_VX[i], D2_VY[i]};
+            for (int j = 0; j < 2; ++j) {
+                double s = sqrt(1.0 + 3.0 * u[j] * u[j]);
+                double base = (2.0 * u[j] + s) / (1.0 - u[j]);
+                double power = 1.0;
+                if (v[j] == 1) power = base;
+                if (v[j] == -1) power = 1.0 / base;
+                prod *= (2.0 - s) * power;
+            }
+            fstar[i] = rho * D2_W[i] * prod;
+        }
+    }
+}
+
+/* ---- nonequilibrium entropy (Sec. 3.2, 3.6) ----------------------------- */
+
+/* h(x) = (1+x) ln(1+x) - x.  With x_i = (f_i - f*_i)/f*_i,
+ *   sum_i f_i ln(f_i/f*_i) = sum_i f*_i h(x_i) + sum_i (f_i - f*_i),
+ * and the last sum vanishes because f and f* share their moments, so
+ * eq. (DelS) equals sum_i f*_i h(x_i).  For small |x| the closed form
+ * cancels, so its Taylor series sum_{n>=2} (-1)^n x^n / (n(n-1)) is used. */
+double orc_h(double x)
+{
+    if (fabs(x) < 0.05) {
+        double sum = 0.0;
+        double power = x * x;
+        for (int n = 2; n < 60; ++n) {
+            double term = power / ((double)n * (double)(n - 1));
+            if (n % 2 == 0)
+                sum += term;
+            else
+                sum -= term;
+            if (fabs(term) <= 1e-20 * fabs(sum)) break;
+            power *= x;
+        }
+        return sum;
+    }
+    return (1.0 + x) * log1p(x) - x;
+}
+
+double orc_delta_s(int32_t q, int32_t form, const double* f,
+                   const double* fstar)
+{
+    for (int i = 0; i < q; ++i)
+        if (isnan(f[i]) || isnan(fstar[i])) return NAN;
+    for (int i = 0; i < q; ++i)
+        if (!(fstar[i] > 0.0)) return INFINITY;
+    double sum = 0.0;
+    if (form == ORC_DS_QUADRATIC) {
+        /* sum_i (f_i - f*_i)^2 / (2 f*_i) */
+        for (int i = 0; i < q; ++i) {
+            double d = f[i] - fstar[i];
+            sum += 0.5 * d * d / fstar[i];
+        }
+        return sum;
+    }
+    for (int i = 0; i < q; ++i)
+        if (!(f[i] > 0.0)) return INFINITY;
+    for (int i = 0; i < q; ++i)
+        sum += fstar[i] * orc_h((f[i] - fstar[i]) / fstar[i]);
+    return sum;
+}
+
+double orc_entropy(int32_t lattice, const double* f)
+{
+    int q = orc_q(lattice);
+    const double* w = lattice == ORC_D1Q3 ? D1_W : D2_W;
+    double s = 0.0;
+    for (int i = 0; i < q; ++i) {
+        if (!(f[i] > 0.0)) return NAN;
+        s -= f[i] * log(f[i] / w[i]);
+    }
+    return s;
+}
+
+/* Sec. 3.5: sort the neighbourhood, take the middle value. */
+double orc_median(const double* v, int32_t n)
+{
+    double a[27];
+    for (int i = 0; i < n; ++i) a[i] = v[i];
+    for (int i = 1; i < n; ++i) {
+        double key = a[i];
+        int j = i - 1;
+        while (j >= 0 && a[j] > key) {
+            a[j + 1] = a[j];
+            --j;
+        }
+        a[j + 1] = key;
+    }
+    return a[n / 2];
+}
+
+/* ---- grid helpers -------------------------------------------------------- */
+
+enum { NODE_FLUID = 0, NODE_WALL = 1, NODE_LID = 2 };
+
+static int node_type(const orc_params* p, int x, int y)
+{
+    if (p->bc != ORC_BC_CAVITY) return NODE_FLUID;
+    if (x == 0 || x == p->nx - 1 || y == 0) return NODE_WALL;
+    if (y == p->ny - 1) return NODE_LID;
+    return NODE_FLUID;
+}
+
+static int wrap(int a, int n)
+{
+    return ((a % n) + n) % n;
+}
+
+static int check_params(const orc_params* p)
+{
+    if (p->lattice != ORC_D1Q3 && p->lattice != ORC_D2Q9) return -1;
+    if (p->nx < 1 || p->ny < 1) return -1;
+    if (p->lattice == ORC_D1Q3 && p->ny != 1) return -1;
+    if (!(p->beta >= 0.0 && p->beta <= 1.0)) return -1;
+    if (!(p->delta_trim >= 0.0) || !(p->delta_median >= 0.0)) return -1;
+    if (p->bc == ORC_BC_CAVITY) {
+        if (p->lattice != ORC_D2Q9 || p->nx < 4 || p->ny < 4) return -1;
+    } else if (p->bc == ORC_BC_TUBE) {
+        if (p->lattice != ORC_D1Q3 || p->nx < 2) return -1;
+    } else if (p->bc != ORC_BC_PERIODIC) {
+        return -1;
+    }
+    return 0;
+}
+
+/* Median stencil of node (x, y); returns the number of points (0: the node
+ * is not filtered).  Cavity rule of Sec. 4.4: boundary nodes are not
+ * filtered, nodes next to the boundary use three nodes along the boundary
+ * (next to two walls: the node and its two inner axis neighbours), all other
+ * nodes the 3x3 neighbourhood. */
+static int median_stencil(const orc_params* p, int x, int y, int* sx, int* sy)
+{
+    int nx = p->nx, ny = p->ny;
+    if (p->lattice == ORC_D1Q3) {
+        if (p->bc == ORC_BC_TUBE && (x == 0 || x == nx - 1)) return 0;
+        for (int k = 0; k < 3; ++k) {
+            sx[k] = wrap(x - 1 + k, nx);
+            sy[k] = 0;
+        }
+        return 3;
+    }
+    if (p->bc == ORC_BC_PERIODIC) {
+        int k = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                sx[k] = wrap(x + dx, nx);
+                sy[k] = wrap(y + dy, ny);
+                ++k;
+            }
+        return 9;
+    }
+    if (node_type(p, x, y) != NODE_FLUID) return 0;
+    int near_l = x == 1, near_r = x == nx - 2;
+    int near_b = y == 1, near_t = y == ny - 2;
+    if ((near_l || near_r) && (near_b || near_t)) {
+        int ix = near_l ? 1 : -1;
+        int iy = near_b ? 1 : -1;
+        sx[0] = x;      sy[0] = y;
+        sx[1] = x + ix; sy[1] = y;
+        sx[2] = x;      sy[2] = y + iy;
+        return 3;
+    }
+    if (near_l || near_r) {
+        for (int k = 0; k < 3; ++k) {
+            sx[k] = x;
+            sy[k] = y - 1 + k;
+        }
+        return 3;
+    }
+    if (near_b || near_t) {
+        for (int k = 0; k < 3; ++k) {
+            sx[k] = x - 1 + k;
+            sy[k] = y;
+        }
+        return 3;
+    }
+    int k = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            sx[k] = x + dx;
+            sy[k] = y + dy;
+            ++k;
+        }
+    return 9;
+}
+
+/* ---- free flight (Sec. 2) ------------------------------------------------ */
+
+int orc_stream(const orc_params* p, const double* o, double* f)
+{
+    if (check_params(p)) return -1;
+    int q = orc_q(p->lattice), nx = p->nx, ny = p->ny, n = nx * ny;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int i = 0; i < q; ++i) {
+                int vx, vy;
+                orc_velocity(p->lattice, i, &vx, &vy);
+                int tx = x + vx, ty = y + vy;
+                double val = o[i * n + y * nx + x];
+                if (p->bc == ORC_BC_PERIODIC) {
+                    tx = wrap(tx, nx);
+                    ty = wrap(ty, ny);
+                    f[i * n + ty * nx + tx] = val;
+                } else if (tx >= 0 && tx < nx && ty >= 0 && ty < ny) {
+                    f[i * n + ty * nx + tx] = val;
+                } else {
+                    /* leaves the grid: comes back reversed at the same node */
+                    int j = orc_opposite(p->lattice, i);
+                    f[j * n + y * nx + x] = val;
+                }
+            }
+    return 0;
+}
+
+int orc_init_equilibrium(const orc_params* p, const double* rho,
+                         const double* u, double* f)
+{
+    if (check_params(p)) return -1;
+    int q = orc_q(p->lattice), n = p->nx * p->ny;
+    double fs[9];
+    for (int s = 0; s < n; ++s) {
+        double uy = p->lattice == ORC_D2Q9 ? u[n + s] : 0.0;
+        orc_equilibrium(p->lattice, p->qe, rho[s], u[s], uy, fs);
+        for (int i = 0; i < q; ++i) f[i * n + s] = fs[i];
+    }
+    return 0;
+}
+
+/* ---- one time step -------------------------------------------------------
+ * eq. (lbgkLB): collide every fluid node toward f*, apply the limiter to the
+ * post-collision state (eq. (LimGenF) with the trimming or median rule),
+ * then free flight.  Cavity walls: bounce-back (reverse all populations, no
+ * collision); lid nodes: set to f*(rho0, (u0, 0)) (Sec. 4.4.1). */
+int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
+             double* dS)
+{
+    if (check_params(p)) return -1;
+    const int q = orc_q(p->lattice), nx = p->nx, ny = p->ny, n = nx * ny;
+    const double c = 2.0 * p->beta - 1.0;
+
+    double* fst = (double*)malloc(sizeof(double) * q * n);
+    double* fpost = (double*)malloc(sizeof(double) * q * n);
+    double* o = (double*)malloc(sizeof(double) * q * n);
+    double* dpre = (double*)malloc(sizeof(double) * n);
+    double* dpost = (double*)malloc(sizeof(double) * n);
+    uint8_t* m = (uint8_t*)calloc(n, 1);
+    if (!fst || !fpost || !o || !dpre || !dpost || !m) {
+        free(fst); free(fpost); free(o); free(dpre); free(dpost); free(m);
+        return -2;
+    }
+
+    orc_stats s;
+    memset(&s, 0, sizeof(s));
+    s.total_entropy = p->entropy ? 0.0 : NAN;
+
+    /* pass 1: moments, collision, Delta S of every node */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            int site = y * nx + x;
+            double fl[9], fs[9], fp[9];
+            double rho = 0.0, jx = 0.0, jy = 0.0;
+            for (int i = 0; i < q; ++i) {
+                int vx, vy;
+                orc_velocity(p->lattice, i, &vx, &vy);
+                fl[i] = f[i * n + site];
+                rho += fl[i];
+                jx += vx * fl[i];
+                jy += vy * fl[i];
+            }
+            s.mass += rho;
+            s.mom_x += jx;
+            s.mom_y += jy;
+            if (!isfinite(rho) || !isfinite(jx) || !isfinite(jy)) s.n_nonfinite++;
+            dpre[site] = 0.0;
+            dpost[site] = 0.0;
+            int type = node_type(p, x, y);
+            if (type == NODE_WALL) {
+                for (int i = 0; i < q; ++i)
+                    o[i * n + site] = fl[orc_opposite(p->lattice, i)];
+                m[site] = ORC_MASK_NOTFLUID;
+                continue;
+            }
+            if (type == NODE_LID) {
+                orc_equilibrium(p->lattice, p->qe, p->rho0, p->lid_ux, 0.0, fs);
+                for (int i = 0; i < q; ++i) o[i * n + site] = fs[i];
+                m[site] = ORC_MASK_NOTFLUID;
+                continue;
+            }
+            s.n_fluid++;
+            double ux = jx / rho, uy = jy / rho;   /* eq. (macro_dis) */
+            orc_equilibrium(p->lattice, p->qe, rho, ux, uy, fs);
+            for (int i = 0; i < q; ++i)          /* eq. (collLBGK) */
+                fp[i] = fs[i] + c * (fs[i] - fl[i]);
+            dpre[site] = orc_delta_s(q, p->ds_form, fl, fs);
+            dpost[site] = orc_delta_s(q, p->ds_form, fp, fs);
+            for (int i = 0; i < q; ++i) {
+                fst[i * n + site] = fs[i];
+                fpost[i * n + site] = fp[i];
+            }
+            if (p->entropy) {
+                double e = orc_entropy(p->lattice, fl);
+                if (isfinite(e)) s.total_entropy += e;
+            }
+        }
+
+    /* pass 2: limiter on the post-collision state */
+    double max_ds = 0.0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            int site = y * nx + x;
+            if (node_type(p, x, y) != NODE_FLUID) continue;
+            double d = dpost[site];
+            double dp = dpre[site];
+            if (isinf(d) || isinf(dp)) {
+                s.n_nonpositive++;
+                m[site] |= ORC_MASK_NONPOS;
+            }
+            if (isfinite(dp)) s.sum_dS_pre += dp;
+            if (isfinite(d)) {
+                s.sum_dS_post += d;
+                if (d > max_ds) max_ds = d;
+            }
+            double phi = 1.0;
+            if (p->limiter & ORC_LIM_TRIM) {
+                /* eq. (entrHom) with Delta S_t = delta, or an Ehrenfests' step */
+                double t = p->delta_trim;
+                if (d > t) {
+                    m[site] |= ORC_MASK_TRIM;
+                    double pt = p->trim_mode == ORC_TRIM_EHRENFEST ? 0.0 : sqrt(t / d);
+                    if (pt < phi) phi = pt;
+                    s.n_trimmed++;
+                }
+            }
+            if (p->limiter & ORC_LIM_MEDIAN) {
+                int sx[9], sy[9];
+                int k = median_stencil(p, x, y, sx, sy);
+                if (k > 0) {
+                    double vals[9];
+                    for (int a = 0; a < k; ++a) vals[a] = dpost[sy[a] * nx + sx[a]];
+                    double med = orc_median(vals, k);
+                    int hit;
+                    double t;
+                    if (p->median_mode == ORC_MED_GATE) {
+                        hit = d > p->delta_median && d > med;
+                        t = med;
+                    } else {
+                        t = med > p->delta_median ? med : p->delta_median;
+                        hit = d > t;
+                    }
+                    if (hit) {
+                        m[site] |= ORC_MASK_MEDIAN;
+                        double pm = sqrt(t / d);
+                        if (pm < phi) phi = pm;
+                        s.n_filtered++;
+                    }
+                }
+            }
+            double fs[9], fl[9];
+            for (int i = 0; i < q; ++i) {       /* eq. (LimGenF) */
+                fs[i] = fst[i * n + site];
+                fl[i] = fs[i] + phi * (fpost[i * n + site] - fs[i]);
+                o[i * n + site] = fl[i];
+            }
+            if (phi < 1.0 && isfinite(d)) {
+                double after = orc_delta_s(q, p->ds_form, fl, fs);
+                s.limiter_production += d - after;
+            }
+        }
+    s.max_dS = max_ds;
+    s.lbgk_production = (1.0 - c * c) * s.sum_dS_pre;
+
+    /* pass 3: free flight */
+    orc_stream(p, o, f);
+
+    if (st) *st = s;
+    if (mask) memcpy(mask, m, n);
+    if (dS) memcpy(dS, dpost, sizeof(double) * n);
+    free(fst); free(fpost); free(o); free(dpre); free(dpost); free(m);
+    return 0;
+}

@@ -1,0 +1,205 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg.  The product package never imports it.
+
+All arrays are numpy float64 in the layout f[i, y, x] (D1Q3: ny = 1); the
+state is the post-streaming (pre-collision) state of eq. (lbgkLB).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+D1Q3, D2Q9 = 1, 2
+QE_POLY, QE_ENTROPIC = 0, 1
+DS_EXACT, DS_QUADRATIC = 0, 1
+LIM_TRIM, LIM_MEDIAN = 1, 2
+TRIM_HOMOTHETY, TRIM_EHRENFEST = 0, 1
+MED_FLOOR, MED_GATE = 0, 1
+BC_PERIODIC, BC_CAVITY, BC_TUBE = 0, 1, 2
+MASK_TRIM, MASK_MEDIAN, MASK_NONPOS, MASK_NOTFLUID = 1, 2, 4, 8
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("beta", ctypes.c_double),
+        ("qe", ctypes.c_int32), ("ds_form", ctypes.c_int32), ("limiter", ctypes.c_int32),
+        ("trim_mode", ctypes.c_int32), ("median_mode", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("delta_trim", ctypes.c_double), ("delta_median", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("lid_ux", ctypes.c_double),
+        ("entropy", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double),
+        ("sum_dS_pre", ctypes.c_double), ("sum_dS_post", ctypes.c_double), ("max_dS", ctypes.c_double),
+        ("lbgk_production", ctypes.c_double), ("limiter_production", ctypes.c_double),
+        ("total_entropy", ctypes.c_double),
+        ("n_trimmed", ctypes.c_int64), ("n_filtered", ctypes.c_int64),
+        ("n_nonpositive", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no FP contraction)."""
+    src = os.path.join(HERE, "oracle.c")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-o", LIB_PATH, src, "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_q.argtypes = [ctypes.c_int32]
+        L.orc_equilibrium.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, dp]
+        L.orc_delta_s.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.orc_delta_s.restype = ctypes.c_double
+        L.orc_h.argtypes = [ctypes.c_double]
+        L.orc_h.restype = ctypes.c_double
+        L.orc_entropy.argtypes = [ctypes.c_int32, dp]
+        L.orc_entropy.restype = ctypes.c_double
+        L.orc_median.argtypes = [dp, ctypes.c_int32]
+        L.orc_median.restype = ctypes.c_double
+        L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Stats),
+                               ctypes.POINTER(ctypes.c_uint8), dp]
+        L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
+        L.orc_init_equilibrium.argtypes = [ctypes.POINTER(Params), dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def q_of(lattice: int) -> int:
+    return 3 if lattice == D1Q3 else 9
+
+
+def velocities(lattice: int):
+    L = lib()
+    q = q_of(lattice)
+    vx, vy = ctypes.c_int32(), ctypes.c_int32()
+    out = []
+    for i in range(q):
+        L.orc_velocity(lattice, i, ctypes.byref(vx), ctypes.byref(vy))
+        out.append((vx.value, vy.value))
+    return np.array(out, dtype=np.int64)
+
+
+def opposite(lattice: int, i: int) -> int:
+    return lib().orc_opposite(lattice, i)
+
+
+def equilibrium(lattice: int, qe: int, rho: float, ux: float, uy: float = 0.0) -> np.ndarray:
+    out = np.zeros(q_of(lattice))
+    lib().orc_equilibrium(lattice, qe, rho, ux, uy, _dp(out))
+    return out
+
+
+def delta_s(form: int, f: np.ndarray, fstar: np.ndarray) -> float:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    fstar = np.ascontiguousarray(fstar, dtype=np.float64)
+    return lib().orc_delta_s(len(f), form, _dp(f), _dp(fstar))
+
+
+def h(x: float) -> float:
+    return lib().orc_h(x)
+
+
+def entropy(lattice: int, f: np.ndarray) -> float:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_entropy(lattice, _dp(f))
+
+
+def median(v) -> float:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().orc_median(_dp(v), len(v))
+
+
+def make_params(lattice=D2Q9, nx=8, ny=8, beta=0.9, qe=QE_POLY, ds_form=DS_EXACT, limiter=0,
+                trim_mode=TRIM_HOMOTHETY, median_mode=MED_FLOOR, bc=BC_PERIODIC, delta_trim=1e-3,
+                delta_median=1e-3, rho0=1.0, lid_ux=0.0, entropy=False) -> Params:
+    if lattice == D1Q3:
+        ny = 1
+    return Params(lattice, nx, ny, beta, qe, ds_form, limiter, trim_mode, median_mode, bc,
+                  delta_trim, delta_median, rho0, lid_ux, 1 if entropy else 0)
+
+
+def init_equilibrium(p: Params, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
+    n = p.nx * p.ny
+    rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(n)
+    dim = 1 if p.lattice == D1Q3 else 2
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(dim * n)
+    f = np.zeros(q_of(p.lattice) * n)
+    rc = lib().orc_init_equilibrium(ctypes.byref(p), _dp(rho), _dp(u), _dp(f))
+    if rc:
+        raise ValueError(f"orc_init_equilibrium failed ({rc})")
+    return f.reshape(q_of(p.lattice), p.ny, p.nx)
+
+
+def step(p: Params, f: np.ndarray, steps: int = 1, record: bool = False):
+    """Advance f in place by `steps` steps; returns (stats of the last step,
+    mask, dS) with mask/dS of the last step when `record` is set."""
+    assert f.dtype == np.float64 and f.flags.c_contiguous
+    n = p.nx * p.ny
+    st = Stats()
+    mask = np.zeros(n, dtype=np.uint8) if record else None
+    ds = np.zeros(n) if record else None
+    L = lib()
+    for k in range(steps):
+        last = k == steps - 1
+        mptr = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if (record and last) else None
+        dptr = _dp(ds) if (record and last) else None
+        rc = L.orc_step(ctypes.byref(p), _dp(f), ctypes.byref(st), mptr, dptr)
+        if rc:
+            raise ValueError(f"orc_step failed ({rc})")
+    if record:
+        return st, mask.reshape(p.ny, p.nx), ds.reshape(p.ny, p.nx)
+    return st, None, None
+
+
+def stream(p: Params, o: np.ndarray) -> np.ndarray:
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    f = np.zeros_like(o)
+    rc = lib().orc_stream(ctypes.byref(p), _dp(o), _dp(f))
+    if rc:
+        raise ValueError("orc_stream failed")
+    return f
+
+
+def moments(lattice: int, f: np.ndarray):
+    """rho and u of every node, eq. (macro_dis), summed in index order."""
+    v = velocities(lattice)
+    rho = np.zeros(f.shape[1:])
+    jx = np.zeros(f.shape[1:])
+    jy = np.zeros(f.shape[1:])
+    for i in range(f.shape[0]):
+        rho += f[i]
+        jx += v[i, 0] * f[i]
+        jy += v[i, 1] * f[i]
+    return rho, jx / rho, jy / rho
