@@ -1,0 +1,215 @@
+/*
+ * lbm.h -- C ABI of the MI355X limited lattice Boltzmann step.
+ *
+ * One time step is the LBGK step of Brownlee, Gorban & Levesley,
+ * "Nonequilibrium entropy limiters in lattice Boltzmann methods"
+ * (Physica A; arXiv:0704.0043), eq. (lbgkLB) of Sec. 4.2:
+ *   free flight (Sec. 2) -> moments rho, u (eq. macro_dis) -> quasiequilibrium
+ *   f* (eqs. polyeq1d, entropiceq1d, polyeq2d, maxwellian of Sec. 4.1) ->
+ *   over-relaxation f' = f* + (2 beta - 1)(f* - f) (eq. collLBGK) ->
+ *   nonequilibrium entropy Delta S(f') = sum f' ln(f'/f*) (eqs. locaNEQentropy,
+ *   Kul, DelS) -> limiter f -> f* + phi (f' - f*) (eq. LimGenF) with
+ *   entropy trimming (Sec. 3.2 Ehrenfests' step, Sec. 3.4 eq. entrHom) and/or
+ *   the median entropy filter (Sec. 3.5, cavity stencils of Sec. 4.4).
+ *
+ * Units are lattice units (dx = dt = 1).  Populations are laid out as
+ * structure-of-arrays planes f[i][y][x], x fastest; for D1Q3 ny = 1.
+ * Velocity order: D1Q3 {0, -1, +1}; D2Q9 {rest, E, N, W, S, NE, NW, SW, SE}.
+ *
+ * Conventions shared by all functions:
+ *  - Every function returns an int status: LBM_OK (0) or a negative code.
+ *    On error, lbm_last_error(ctx) holds a message (ctx may be NULL for
+ *    errors raised before a context exists; then a thread-local message is
+ *    kept).  No function aborts or exits the process.
+ *  - Host arrays are owned by the caller.  Inputs are copied during the
+ *    call; outputs are written into caller-allocated arrays of the stated
+ *    size.  Device memory is owned by the library unless the caller passes
+ *    a workspace (then the caller keeps ownership and must keep it alive
+ *    until lbm_destroy).
+ *  - A context is used by one host thread at a time.
+ *  - The "state at step t" is the post-free-flight (pre-collision) state
+ *    f(x, t) of eq. (lbgkLB).  lbm_step is asynchronous with respect to the
+ *    host (stream ordered); functions documented "sync" wait for the stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+#if defined(__GNUC__)
+#define LBM_API __attribute__((visibility("default")))
+#else
+#define LBM_API
+#endif
+
+/* status codes */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument (sizes, beta, delta, enums, NULL) */
+#define LBM_ENOMEM (-2)    /* device allocation failed or workspace too small */
+#define LBM_EDEVICE (-3)   /* a HIP runtime error; message in lbm_last_error */
+#define LBM_EUNSTABLE (-4) /* non-finite moments seen at a stats point */
+#define LBM_ERANGE (-5)    /* domain index out of range */
+
+/* lattice (Sec. 4.1) */
+enum lbm_lattice { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
+/* quasiequilibrium: polynomial (polyeq1d/polyeq2d) or entropic
+ * (entropiceq1d/maxwellian).  The D1Q3 entropic movers are taken with the
+ * velocity they are labelled by: f*(v=+-1) = (rho/6)(+-3u - 1 + 2 sqrt(1+3u^2)). */
+enum lbm_qe { LBM_QE_POLYNOMIAL = 0, LBM_QE_ENTROPIC = 1 };
+/* limiter families, a bit mask: trimming (Sec. 3.2/3.4), median filter (Sec. 3.5) */
+enum lbm_limiter { LBM_LIM_NONE = 0, LBM_LIM_TRIM = 1, LBM_LIM_MEDIAN = 2 };
+/* trimming: homothety to Delta S_t = delta (eq. entrHom) or Ehrenfests' step
+ * f -> f* (Sec. 3.2) at sites with Delta S > delta */
+enum lbm_trimmode { LBM_TRIM_HOMOTHETY = 0, LBM_TRIM_EHRENFEST = 1 };
+/* median tolerance: FLOOR uses Delta S_t = max(Delta S_med, delta);
+ * GATE corrects to Delta S_med only where Delta S > delta */
+enum lbm_medmode { LBM_MED_FLOOR_DELTA = 0, LBM_MED_GATE_DELTA = 1 };
+/* Delta S form: EXACT = sum f ln(f/f*) (eq. DelS / Kul), QUADRATIC =
+ * sum (f - f*)^2 / (2 f*) (its second-order expansion, Sec. 3.6) */
+enum lbm_dsform { LBM_DS_EXACT = 0, LBM_DS_QUADRATIC = 1 };
+/* boundaries: periodic; lid-driven cavity with on-node bounce-back walls and
+ * a constant equilibrium lid (Sec. 4.4.1); 1-D tube with half-way
+ * bounce-back ends (Sec. 4.3) */
+enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_CAVITY = 1, LBM_BC_TUBE_ENDS = 2 };
+/* population storage.  F64 stores f.  The others store the shift
+ * g_i = f_i - w_i rho0 (w_i the lattice weights at rest) and compute in FP32;
+ * global reductions are FP64 in every mode. */
+enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT = 3 };
+
+/* limiter mask bits reported per node by lbm_limiter_mask */
+#define LBM_MASK_TRIM 1u     /* Delta S' > trimming threshold */
+#define LBM_MASK_MEDIAN 2u   /* median filter corrected the site */
+#define LBM_MASK_NONPOS 4u   /* a population or f* was <= 0 (Delta S = +inf) */
+#define LBM_MASK_NOTFLUID 8u /* wall or lid node: no collision, no limiter */
+
+/* run flags */
+#define LBM_RUN_RECORD 1u    /* keep per-node mask and Delta S' of every step */
+#define LBM_RUN_ENTROPY 2u   /* also accumulate sum S(f) (Sec. 4.3.1) */
+#define LBM_RUN_NO_GRAPH 4u  /* launch steps one by one (no hipGraph) */
+#define LBM_RUN_NO_TUNE 8u   /* skip the tile autotuner when tile_x == 0 */
+
+/* One simulation domain.  All domains of one context share lattice, qe,
+ * ds_form and bc (they run in the same kernel); sizes, beta, limiter and
+ * thresholds may differ per domain. */
+typedef struct {
+    uint32_t struct_size;       /* = sizeof(lbm_domain_desc) */
+    int32_t lattice;            /* enum lbm_lattice */
+    int32_t nx, ny;             /* grid nodes; ny = 1 for D1Q3.  Cavity: nx, ny >= 4 */
+    double beta;                /* over-relaxation, 0 <= beta <= 1 (eq. collLBGK) */
+    int32_t qe;                 /* enum lbm_qe */
+    int32_t limiter;            /* bit mask of enum lbm_limiter */
+    int32_t trim_mode;          /* enum lbm_trimmode */
+    int32_t median_mode;        /* enum lbm_medmode */
+    int32_t ds_form;            /* enum lbm_dsform */
+    int32_t bc;                 /* enum lbm_bc */
+    double delta_trim;          /* trimming threshold delta >= 0 */
+    double delta_median;        /* median tolerance delta >= 0 */
+    double rho0;                /* reference density: storage shift, cavity lid density */
+    double lid_ux;              /* cavity lid velocity u0 (lid state f*(rho0, (u0, 0))) */
+    const double* rho_init;     /* nullable host [ny*nx]: initial density (default rho0) */
+    const double* u_init;       /* nullable host [dim][ny*nx]: initial velocity (default 0) */
+    const double* f_init;       /* nullable host [Q][ny*nx]: initial state, overrides rho/u */
+    int32_t probe_x, probe_y;   /* node whose (ux, uy) is recorded each step; -1 = none */
+} lbm_domain_desc;
+
+typedef struct {
+    uint32_t struct_size;       /* = sizeof(lbm_run_desc) */
+    int32_t storage;            /* enum lbm_storage */
+    int32_t device;             /* HIP device ordinal */
+    int32_t stats_every;        /* >0: lbm_step synchronises every k steps and
+                                   returns LBM_EUNSTABLE on non-finite moments */
+    int32_t tile_x, tile_y;     /* workgroup shape (tile_x * tile_y = 256);
+                                   0 = chosen by the autotuner */
+    int32_t tile_h;             /* rows per workgroup tile; 0 = autotuned */
+    uint32_t flags;             /* LBM_RUN_* */
+    int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
+    int32_t graph_chunk;        /* steps per captured graph (even), 0 = 64 */
+    void* stream;               /* hipStream_t to run on; NULL = library-owned stream */
+    void* workspace;            /* nullable device buffer (caller-owned) */
+    size_t workspace_bytes;     /* its size; must be >= lbm_workspace_bytes() */
+} lbm_run_desc;
+
+typedef struct {
+    uint32_t struct_size;       /* = sizeof(lbm_entropy_stats_t) */
+    int64_t step;               /* number of completed steps; the sums below
+                                   describe the last one (its input state) */
+    double mass, mom_x, mom_y;  /* sum rho, sum rho u over all nodes */
+    double sum_dS_pre;          /* sum over fluid nodes of Delta S(f) before collision */
+    double sum_dS_post;         /* ... of Delta S(f') after collision */
+    double max_dS;              /* max Delta S(f') (finite values) */
+    double mean_dS;             /* sum_dS_post / n_fluid */
+    double lbgk_production;     /* [1 - (2 beta - 1)^2] sum_dS_pre (Sec. 3.4) */
+    double limiter_production;  /* sum (Delta S(f') - Delta S(f_limited)) (eq. LimEntLim) */
+    double total_entropy;       /* sum S(f), S = -sum f ln(f/W); NaN unless LBM_RUN_ENTROPY */
+    int64_t n_trimmed, n_filtered, n_nonpositive, n_nonfinite, n_fluid;
+} lbm_entropy_stats_t;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Device bytes a context needs (for a caller-provided workspace). */
+LBM_API int lbm_workspace_bytes(const lbm_domain_desc* domains, int32_t n_domains,
+                        const lbm_run_desc* run, size_t* bytes);
+
+/* Create a context: validates the descriptors, allocates (or carves the
+ * workspace into) population buffers, builds f(x, 0) (f_init, or f*(rho, u)),
+ * and tunes the tile shape.  Errors: EINVAL, ENOMEM, EDEVICE.  On error
+ * *out is NULL and nothing is leaked. */
+LBM_API int lbm_create(const lbm_domain_desc* domains, int32_t n_domains,
+               const lbm_run_desc* run, lbm_ctx** out);
+
+/* Advance every domain by n_steps >= 0 time steps (async, stream ordered). */
+LBM_API int lbm_step(lbm_ctx* ctx, int64_t n_steps);
+
+/* Wait for all queued work. */
+LBM_API int lbm_synchronize(lbm_ctx* ctx);
+
+/* sync.  rho [ny*nx], u [dim][ny*nx] (dim = 1 for D1Q3) of the current state;
+ * either pointer may be NULL. */
+LBM_API int lbm_moments(lbm_ctx* ctx, int32_t domain, double* rho, double* u);
+
+/* sync.  Global sums of the last completed step (FP64).  Returns
+ * LBM_EUNSTABLE (with *out filled) when n_nonfinite > 0. */
+LBM_API int lbm_entropy_stats(lbm_ctx* ctx, int32_t domain, lbm_entropy_stats_t* out);
+
+/* sync.  Current state f[Q][ny*nx] as FP64 (reduced storage is widened). */
+LBM_API int lbm_get_populations(lbm_ctx* ctx, int32_t domain, double* f);
+
+/* sync.  Replace the current state with f[Q][ny*nx] (rounded to storage). */
+LBM_API int lbm_set_populations(lbm_ctx* ctx, int32_t domain, const double* f);
+
+/* sync.  Per-node limiter mask (LBM_MASK_* bits) and Delta S(f') of the last
+ * step, [ny*nx] each; either pointer may be NULL.  Needs LBM_RUN_RECORD,
+ * else LBM_EINVAL. */
+LBM_API int lbm_limiter_mask(lbm_ctx* ctx, int32_t domain, uint8_t* mask, double* dS);
+
+/* sync.  Probe samples (ux, uy) pairs, oldest first: writes
+ * min(steps done, capacity, max_samples) pairs into uv[2*max_samples]. */
+LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples,
+                    int64_t* n_written);
+
+/* Tile shape in use (after autotuning). */
+LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
+
+/* Release everything the context owns.  NULL is accepted. */
+LBM_API void lbm_destroy(lbm_ctx* ctx);
+
+LBM_API const char* lbm_last_error(const lbm_ctx* ctx);
+LBM_API const char* lbm_strerror(int code);
+
+/* beta for kinematic viscosity nu with c_s^2 = 1/3: nu = (1/3)(1/(2 beta) - 1/2),
+ * i.e. beta = 1/(6 nu + 1) (the LBGK viscosity of Sec. 2 for these lattices). */
+LBM_API double lbm_beta_from_nu(double nu);
+
+LBM_API int lbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,778 @@
+// Host runtime and C ABI of the limited lattice Boltzmann step (see lbm.h).
+//
+// Owns the device memory of a context (or carves a caller workspace), builds
+// the tile table of the step kernels (XCD-aware order), tunes the tile shape,
+// captures chunks of steps into hipGraphs, and reads back state and stats.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_common.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int q_of(int lattice) { return lattice == LBM_D2Q9 ? 9 : 3; }
+
+size_t elem_size(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    default: return 2;
+    }
+}
+
+struct DomainHost {
+    lbm_domain_desc d;     // copy without host pointers
+    int q = 0;
+    long long plane = 0;
+    size_t n = 0;
+    size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0;
+    double shift = 0;
+    int tile_first = 0, tile_count = 0;
+};
+
+struct Layout {
+    size_t off_dom = 0, off_tiles = 0, off_partials = 0, off_counter = 0, off_stage = 0, total = 0;
+    int max_tiles = 0;
+    size_t max_n = 0;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int storage = LBM_F32, lattice = LBM_D2Q9, qe = 0, ds = 0, bc = 0;
+    unsigned flags = 0;
+    int stats_every = 0, probe_cap = 4096, graph_chunk = 64;
+    std::vector<DomainHost> dom;
+    Layout lay;
+    char* ws = nullptr;
+    bool own_ws = false;
+    int tx = 256, ty = 1, th = 64;
+    int ntiles = 0;
+    long long steps_done = 0, finalized_for = -1;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err;
+    std::vector<double> tune_log;   // (tx, th, us) triples
+    std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
+    std::vector<DomainDev> dom_host;
+
+    DomainDev* d_dom() const { return reinterpret_cast<DomainDev*>(ws + lay.off_dom); }
+    Tile* d_tiles() const { return reinterpret_cast<Tile*>(ws + lay.off_tiles); }
+    double* d_partials() const { return reinterpret_cast<double*>(ws + lay.off_partials); }
+    long long* d_counter() const { return reinterpret_cast<long long*>(ws + lay.off_counter); }
+    double* d_stage() const { return reinterpret_cast<double*>(ws + lay.off_stage); }
+};
+
+namespace {
+
+int fail(lbm_ctx* ctx, int code, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
+{
+    if (!doms || nd < 1 || !run) return fail(nullptr, LBM_EINVAL, "domains/run must be non-NULL, n_domains >= 1");
+    if (run->struct_size < sizeof(lbm_run_desc)) return fail(nullptr, LBM_EINVAL, "lbm_run_desc.struct_size too small");
+    if (run->storage < LBM_F64 || run->storage > LBM_BF16_SHIFT) return fail(nullptr, LBM_EINVAL, "bad storage");
+    if (run->tile_x != 0 && run->tile_x != 64 && run->tile_x != 128 && run->tile_x != 256)
+        return fail(nullptr, LBM_EINVAL, "tile_x must be 0, 64, 128 or 256");
+    if (run->tile_x != 0 && run->tile_y != 0 && run->tile_x * run->tile_y != kThreads)
+        return fail(nullptr, LBM_EINVAL, "tile_x * tile_y must be 256");
+    if (run->tile_h < 0 || run->tile_h > kMaxTileH) return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 510]");
+    if (run->graph_chunk < 0 || (run->graph_chunk % 2) != 0) return fail(nullptr, LBM_EINVAL, "graph_chunk must be even");
+    if (run->probe_capacity < 0) return fail(nullptr, LBM_EINVAL, "probe_capacity < 0");
+    const lbm_domain_desc& d0 = doms[0];
+    for (int k = 0; k < nd; ++k) {
+        const lbm_domain_desc& d = doms[k];
+        const std::string where = "domain " + std::to_string(k) + ": ";
+        if (d.struct_size < sizeof(lbm_domain_desc)) return fail(nullptr, LBM_EINVAL, where + "struct_size too small");
+        if (d.lattice != LBM_D1Q3 && d.lattice != LBM_D2Q9) return fail(nullptr, LBM_EINVAL, where + "bad lattice");
+        if (d.lattice != d0.lattice || d.qe != d0.qe || d.ds_form != d0.ds_form || d.bc != d0.bc)
+            return fail(nullptr, LBM_EINVAL, where + "lattice, qe, ds_form and bc must match across domains");
+        if (d.qe != LBM_QE_POLYNOMIAL && d.qe != LBM_QE_ENTROPIC) return fail(nullptr, LBM_EINVAL, where + "bad qe");
+        if (d.ds_form != LBM_DS_EXACT && d.ds_form != LBM_DS_QUADRATIC) return fail(nullptr, LBM_EINVAL, where + "bad ds_form");
+        if (d.limiter < 0 || d.limiter > 3) return fail(nullptr, LBM_EINVAL, where + "bad limiter mask");
+        if (d.trim_mode != 0 && d.trim_mode != 1) return fail(nullptr, LBM_EINVAL, where + "bad trim_mode");
+        if (d.median_mode != 0 && d.median_mode != 1) return fail(nullptr, LBM_EINVAL, where + "bad median_mode");
+        if (d.nx < 1 || d.ny < 1) return fail(nullptr, LBM_EINVAL, where + "nx, ny must be >= 1");
+        if ((long long)d.nx * d.ny * q_of(d.lattice) >= (1LL << 31))
+            return fail(nullptr, LBM_EINVAL, where + "grid too large (Q*nx*ny must be < 2^31)");
+        if (d.lattice == LBM_D1Q3) {
+            if (d.ny != 1) return fail(nullptr, LBM_EINVAL, where + "D1Q3 needs ny = 1");
+            if (d.bc != LBM_BC_PERIODIC && d.bc != LBM_BC_TUBE_ENDS)
+                return fail(nullptr, LBM_EINVAL, where + "D1Q3 supports periodic or tube ends");
+            if (d.bc == LBM_BC_TUBE_ENDS && d.nx < 2) return fail(nullptr, LBM_EINVAL, where + "tube needs nx >= 2");
+        } else {
+            if (d.bc != LBM_BC_PERIODIC && d.bc != LBM_BC_CAVITY)
+                return fail(nullptr, LBM_EINVAL, where + "D2Q9 supports periodic or cavity");
+            if (d.bc == LBM_BC_CAVITY && (d.nx < 4 || d.ny < 4))
+                return fail(nullptr, LBM_EINVAL, where + "cavity needs nx, ny >= 4");
+        }
+        if (!(d.beta >= 0.0 && d.beta <= 1.0)) return fail(nullptr, LBM_EINVAL, where + "beta must be in [0, 1]");
+        if (!(d.delta_trim >= 0.0) || !finite(d.delta_trim) || !(d.delta_median >= 0.0) || !finite(d.delta_median))
+            return fail(nullptr, LBM_EINVAL, where + "delta must be finite and >= 0");
+        if (!(d.rho0 > 0.0) || !finite(d.rho0)) return fail(nullptr, LBM_EINVAL, where + "rho0 must be finite and > 0");
+        if (!finite(d.lid_ux)) return fail(nullptr, LBM_EINVAL, where + "lid_ux not finite");
+        if (d.qe == LBM_QE_ENTROPIC && d.bc == LBM_BC_CAVITY && std::fabs(d.lid_ux) >= 1.0)
+            return fail(nullptr, LBM_EINVAL, where + "entropic f* needs |lid_ux| < 1");
+        if (d.probe_x >= 0 || d.probe_y >= 0) {
+            const bool in = d.probe_x >= 0 && d.probe_x < d.nx && d.probe_y >= 0 && d.probe_y < d.ny;
+            const bool fluid = d.bc != LBM_BC_CAVITY ||
+                               (d.probe_x >= 1 && d.probe_x <= d.nx - 2 && d.probe_y >= 1 && d.probe_y <= d.ny - 2);
+            if (!in || !fluid) return fail(nullptr, LBM_EINVAL, where + "probe must be a fluid node of the grid");
+        }
+        const size_t n = size_t(d.nx) * d.ny;
+        const int dim = d.lattice == LBM_D2Q9 ? 2 : 1;
+        if (d.f_init) {
+            for (size_t s = 0; s < n * q_of(d.lattice); ++s)
+                if (!finite(d.f_init[s])) return fail(nullptr, LBM_EINVAL, where + "f_init has non-finite values");
+        } else {
+            if (d.rho_init)
+                for (size_t s = 0; s < n; ++s)
+                    if (!(d.rho_init[s] > 0.0) || !finite(d.rho_init[s]))
+                        return fail(nullptr, LBM_EINVAL, where + "rho_init must be finite and > 0");
+            if (d.u_init)
+                for (size_t s = 0; s < n * dim; ++s) {
+                    if (!finite(d.u_init[s])) return fail(nullptr, LBM_EINVAL, where + "u_init not finite");
+                    if (d.qe == LBM_QE_ENTROPIC && std::fabs(d.u_init[s]) >= 1.0)
+                        return fail(nullptr, LBM_EINVAL, where + "entropic f* needs |u| < 1");
+                }
+        }
+    }
+    return LBM_OK;
+}
+
+// Device layout for the given descriptors.  The tile arrays are sized for the
+// smallest tile shape so any autotuned shape fits.
+void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run, Layout& L)
+{
+    const int storage = run->storage;
+    const size_t es = elem_size(storage);
+    const unsigned flags = run->flags;
+    const int cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;
+    size_t off = 0;
+    L.max_tiles = 0;
+    L.max_n = 0;
+    dh.resize(nd);
+    for (int k = 0; k < nd; ++k) {
+        DomainHost& h = dh[k];
+        h.d = doms[k];
+        h.d.rho_init = h.d.u_init = h.d.f_init = nullptr;
+        h.q = q_of(h.d.lattice);
+        h.n = size_t(h.d.nx) * h.d.ny;
+        h.plane = (long long)align_up(h.n, 64);
+        h.shift = storage == LBM_F64 ? 0.0 : h.d.rho0;
+        for (int b = 0; b < 2; ++b) {
+            h.off_buf[b] = off;
+            off = align_up(off + size_t(h.q) * h.plane * es, kAlign);
+        }
+        if (flags & LBM_RUN_RECORD) {
+            h.off_mask = off;
+            off = align_up(off + h.n, kAlign);
+            h.off_ds = off;
+            off = align_up(off + h.n * 8, kAlign);
+        }
+        if (h.d.probe_x >= 0) {
+            h.off_probe = off;
+            off = align_up(off + size_t(cap) * 2 * sizeof(float), kAlign);
+        }
+        h.off_stats = off;
+        off = align_up(off + (kNStat + 1) * sizeof(double), kAlign);
+        const int tiles = h.d.lattice == LBM_D2Q9
+                              ? ((h.d.nx + 63) / 64) * ((h.d.ny + 15) / 16)
+                              : (h.d.nx + kThreads - 3) / (kThreads - 2);
+        L.max_tiles += tiles;
+        L.max_n = std::max(L.max_n, h.n);
+    }
+    L.off_dom = off;
+    off = align_up(off + nd * sizeof(DomainDev), kAlign);
+    L.off_tiles = off;
+    off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
+    L.off_partials = off;
+    off = align_up(off + size_t(2) * L.max_tiles * kNStat * sizeof(double), kAlign);
+    L.off_counter = off;
+    off = align_up(off + 2 * sizeof(long long), kAlign);
+    L.off_stage = off;
+    off = align_up(off + size_t(q_of(doms[0].lattice) + 3) * L.max_n * sizeof(double), kAlign);
+    L.total = off;
+}
+
+// Spatial tile order: domain, row chunk, column strip.  The table is indexed
+// by block id; xcd_spatial() gives each block its spatial tile, so every XCD
+// runs one contiguous stretch of the grid (strips sharing halo columns and
+// chunks sharing halo rows hit the same L2) while per-domain partial ranges
+// stay contiguous in spatial order.
+std::vector<Tile> build_tiles(lbm_ctx* ctx, int tx, int th)
+{
+    std::vector<Tile> spatial;
+    for (size_t k = 0; k < ctx->dom.size(); ++k) {
+        DomainHost& h = ctx->dom[k];
+        h.tile_first = int(spatial.size());
+        if (ctx->lattice == LBM_D2Q9) {
+            const int h_rows = std::min(th, h.d.ny);
+            for (int y0 = 0; y0 < h.d.ny; y0 += h_rows)
+                for (int x0 = 0; x0 < h.d.nx; x0 += tx)
+                    spatial.push_back(Tile{int(k), x0, y0, std::min(y0 + h_rows, h.d.ny)});
+        } else {
+            for (int x0 = 0; x0 < h.d.nx; x0 += kThreads - 2) spatial.push_back(Tile{int(k), x0, 0, 1});
+        }
+        h.tile_count = int(spatial.size()) - h.tile_first;
+    }
+    const int T = int(spatial.size());
+    std::vector<Tile> by_block(T);
+    for (int b = 0; b < T; ++b) by_block[b] = spatial[xcd_spatial(b, T)];
+    return by_block;
+}
+
+int upload_domains(lbm_ctx* ctx)
+{
+    std::vector<DomainDev>& dd = ctx->dom_host;
+    dd.assign(ctx->dom.size(), DomainDev{});
+    for (size_t k = 0; k < ctx->dom.size(); ++k) {
+        const DomainHost& h = ctx->dom[k];
+        DomainDev& d = dd[k];
+        d.buf[0] = ctx->ws + h.off_buf[0];
+        d.buf[1] = ctx->ws + h.off_buf[1];
+        d.plane = h.plane;
+        d.nx = h.d.nx;
+        d.ny = h.d.ny;
+        d.c = 2.0 * h.d.beta - 1.0;
+        d.shift = h.shift;
+        d.delta_trim = h.d.delta_trim;
+        d.delta_median = h.d.delta_median;
+        d.rho0 = h.d.rho0;
+        d.lid_ux = h.d.lid_ux;
+        d.limiter = h.d.limiter;
+        d.trim_mode = h.d.trim_mode;
+        d.median_mode = h.d.median_mode;
+        d.probe_x = h.d.probe_x >= 0 ? h.d.probe_x : -1;
+        d.probe_y = h.d.probe_x >= 0 ? h.d.probe_y : -1;
+        d.probe_cap = ctx->probe_cap;
+        d.probe = h.d.probe_x >= 0 ? reinterpret_cast<float*>(ctx->ws + h.off_probe) : nullptr;
+        d.mask = (ctx->flags & LBM_RUN_RECORD) ? reinterpret_cast<unsigned char*>(ctx->ws + h.off_mask) : nullptr;
+        d.dS = (ctx->flags & LBM_RUN_RECORD) ? reinterpret_cast<double*>(ctx->ws + h.off_ds) : nullptr;
+        d.tile_first = h.tile_first;
+        d.tile_count = h.tile_count;
+        d.stats = reinterpret_cast<double*>(ctx->ws + h.off_stats);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_dom(), dd.data(), dd.size() * sizeof(DomainDev), hipMemcpyHostToDevice,
+                                ctx->stream));
+    return LBM_OK;
+}
+
+int set_tiles(lbm_ctx* ctx, int tx, int th)
+{
+    ctx->tiles_host = build_tiles(ctx, tx, th);
+    if (int(ctx->tiles_host.size()) > ctx->lay.max_tiles) return fail(ctx, LBM_EINVAL, "tile table overflow");
+    ctx->ntiles = int(ctx->tiles_host.size());
+    ctx->tx = tx;
+    ctx->ty = kThreads / tx;
+    ctx->th = th;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tiles(), ctx->tiles_host.data(), ctx->tiles_host.size() * sizeof(Tile),
+                                hipMemcpyHostToDevice, ctx->stream));
+    int rc = upload_domains(ctx);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+StepArgs step_args(const lbm_ctx* ctx, int parity)
+{
+    StepArgs a;
+    a.dom = ctx->d_dom();
+    a.tiles = ctx->d_tiles();
+    a.ntiles = ctx->ntiles;
+    a.ndomains = int(ctx->dom.size());
+    a.parity = parity;
+    a.flags = ctx->flags & (LBM_RUN_RECORD | LBM_RUN_ENTROPY);
+    a.partials = ctx->d_partials();
+    a.counter = ctx->d_counter();
+    a.tile_w = ctx->lattice == LBM_D2Q9 ? ctx->tx : kThreads - 2;
+    return a;
+}
+
+int launch_one(lbm_ctx* ctx, int parity)
+{
+    const StepArgs a = step_args(ctx, parity);
+    hipError_t e;
+    if (ctx->lattice == LBM_D2Q9)
+        e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->tx, ctx->ty, ctx->th, ctx->stream);
+    else
+        e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// counter[p] holds the index of the next step when that step reads buffer p
+int reset_counters(lbm_ctx* ctx)
+{
+    long long c[2];
+    c[ctx->steps_done % 2] = ctx->steps_done;
+    c[1 - ctx->steps_done % 2] = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_counter(), c, sizeof(c), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* ctx)
+{
+    for (auto& g : ctx->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Time candidate tile shapes on the live state (reads buffer 0, writes
+// buffer 1, which the first real step overwrites anyway).
+int autotune(lbm_ctx* ctx, int fixed_tx, int fixed_th)
+{
+    std::vector<int> txs = fixed_tx ? std::vector<int>{fixed_tx} : std::vector<int>{256, 128, 64};
+    int max_ny = 0;
+    for (const auto& h : ctx->dom) max_ny = std::max(max_ny, h.d.ny);
+    std::vector<int> ths;
+    if (fixed_th) {
+        ths.push_back(fixed_th);
+    } else {
+        for (int th : {16, 32, 64, 128, 256, 510})
+            if (th <= std::max(16, max_ny)) ths.push_back(th);
+        if (max_ny < 510 && std::find(ths.begin(), ths.end(), max_ny) == ths.end() && max_ny >= 16)
+            ths.push_back(max_ny);
+    }
+    if (txs.size() * ths.size() == 1 || (ctx->flags & LBM_RUN_NO_TUNE)) {
+        return set_tiles(ctx, txs[0], ths.size() == 1 ? ths[0] : std::min(64, std::max(16, max_ny)));
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    double best = 1e300;
+    int btx = txs[0], bth = ths[0];
+    for (int tx : txs)
+        for (int th : ths) {
+            int rc = set_tiles(ctx, tx, th);
+            if (rc) return rc;
+            for (int w = 0; w < 2; ++w)
+                if ((rc = launch_one(ctx, 0))) return rc;
+            const int reps = 5;
+            HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+            for (int r = 0; r < reps; ++r)
+                if ((rc = launch_one(ctx, 0))) return rc;
+            HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+            HIP_TRY(ctx, hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1000.0 * ms / reps;
+            ctx->tune_log.push_back(tx);
+            ctx->tune_log.push_back(th);
+            ctx->tune_log.push_back(us);
+            if (us < best) {
+                best = us;
+                btx = tx;
+                bth = th;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return set_tiles(ctx, btx, bth);
+}
+
+int capture(lbm_ctx* ctx, int parity)
+{
+    hipGraph_t g = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_OK;
+    for (int k = 0; k < ctx->graph_chunk && rc == LBM_OK; ++k) rc = launch_one(ctx, (parity + k) % 2);
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&ctx->graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int check_domain(lbm_ctx* ctx, int32_t d)
+{
+    if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
+    if (d < 0 || d >= int(ctx->dom.size())) return fail(ctx, LBM_ERANGE, "domain index out of range");
+    return LBM_OK;
+}
+
+int finalize_stats(lbm_ctx* ctx)
+{
+    if (ctx->steps_done == 0 || ctx->finalized_for == ctx->steps_done) return LBM_OK;
+    const StepArgs a = step_args(ctx, 0);
+    hipError_t e = launch_finalize(a, int((ctx->steps_done - 1) % 2), ctx->steps_done, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("finalize: ") + hipGetErrorString(e));
+    ctx->finalized_for = ctx->steps_done;
+    return LBM_OK;
+}
+
+int read_stats(lbm_ctx* ctx, int32_t d, lbm_entropy_stats_t* out)
+{
+    int rc = finalize_stats(ctx);
+    if (rc) return rc;
+    const DomainHost& h = ctx->dom[d];
+    double raw[kNStat + 1];
+    std::memset(raw, 0, sizeof(raw));
+    if (ctx->steps_done > 0) {
+        HIP_TRY(ctx, hipMemcpyAsync(raw, ctx->ws + h.off_stats, sizeof(raw), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    lbm_entropy_stats_t s;
+    std::memset(&s, 0, sizeof(s));
+    s.struct_size = sizeof(s);
+    s.step = ctx->steps_done;
+    const double c = 2.0 * h.d.beta - 1.0;
+    s.mass = raw[kSMass] + (ctx->steps_done > 0 ? h.shift * double(h.n) : 0.0);
+    s.mom_x = raw[kSJx];
+    s.mom_y = raw[kSJy];
+    s.sum_dS_pre = raw[kSDpre];
+    s.sum_dS_post = raw[kSDpost];
+    s.max_dS = raw[kSMax];
+    s.n_fluid = (int64_t)raw[kSFluid];
+    s.mean_dS = s.n_fluid > 0 ? s.sum_dS_post / double(s.n_fluid) : 0.0;
+    s.lbgk_production = (1.0 - c * c) * s.sum_dS_pre;
+    s.limiter_production = raw[kSLim];
+    s.total_entropy = (ctx->flags & LBM_RUN_ENTROPY) ? raw[kSEnt] : NAN;
+    s.n_trimmed = (int64_t)raw[kSTrim];
+    s.n_filtered = (int64_t)raw[kSFilt];
+    s.n_nonpositive = (int64_t)raw[kSNonpos];
+    s.n_nonfinite = (int64_t)raw[kSNonfin];
+    if (out) {
+        const uint32_t keep = out->struct_size ? std::min<uint32_t>(out->struct_size, sizeof(s)) : sizeof(s);
+        std::memcpy(out, &s, keep);
+    }
+    return s.n_nonfinite > 0 ? fail(ctx, LBM_EUNSTABLE, "non-finite moments in the last step") : LBM_OK;
+}
+
+void release(lbm_ctx* ctx)
+{
+    if (!ctx) return;
+    drop_graphs(ctx);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+double lbm_beta_from_nu(double nu) { return 1.0 / (6.0 * nu + 1.0); }
+
+const char* lbm_strerror(int code)
+{
+    switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of device memory or workspace too small";
+    case LBM_EDEVICE: return "HIP device error";
+    case LBM_EUNSTABLE: return "non-finite moments (unstable run)";
+    case LBM_ERANGE: return "domain index out of range";
+    }
+    return "unknown error";
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx)
+{
+    if (ctx && !ctx->err.empty()) return ctx->err.c_str();
+    return g_err.c_str();
+}
+
+int lbm_workspace_bytes(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_desc* run, size_t* bytes)
+{
+    int rc = validate(domains, n_domains, run);
+    if (rc) return rc;
+    if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
+    std::vector<DomainHost> dh;
+    Layout L;
+    plan(dh, domains, n_domains, run, L);
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_desc* run, lbm_ctx** out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(domains, n_domains, run);
+    if (rc) return rc;
+    lbm_ctx* ctx = new lbm_ctx();
+    ctx->device = run->device;
+    ctx->storage = run->storage;
+    ctx->lattice = domains[0].lattice;
+    ctx->qe = domains[0].qe;
+    ctx->ds = domains[0].ds_form;
+    ctx->bc = domains[0].bc;
+    ctx->flags = run->flags;
+    ctx->stats_every = run->stats_every;
+    ctx->probe_cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;
+    ctx->graph_chunk = run->graph_chunk > 0 ? run->graph_chunk : 64;
+    plan(ctx->dom, domains, n_domains, run, ctx->lay);
+
+    auto bail = [&](int code) {
+        release(ctx);
+        return code;
+    };
+    hipError_t e = hipSetDevice(run->device);
+    if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e)));
+    if (run->stream) {
+        ctx->stream = static_cast<hipStream_t>(run->stream);
+    } else {
+        e = hipStreamCreate(&ctx->stream);
+        if (e != hipSuccess)
+            return bail(fail(nullptr, LBM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e)));
+        ctx->own_stream = true;
+    }
+    if (run->workspace) {
+        if (run->workspace_bytes < ctx->lay.total)
+            return bail(fail(nullptr, LBM_ENOMEM, "workspace smaller than lbm_workspace_bytes()"));
+        if (reinterpret_cast<uintptr_t>(run->workspace) % kAlign)
+            return bail(fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned"));
+        ctx->ws = static_cast<char*>(run->workspace);
+    } else {
+        e = hipMalloc(reinterpret_cast<void**>(&ctx->ws), ctx->lay.total);
+        if (e != hipSuccess) {
+            ctx->ws = nullptr;
+            return bail(fail(nullptr, LBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)));
+        }
+        ctx->own_ws = true;
+    }
+
+    // initial state f(x, 0) in FP64, converted into buffer 0
+    double* stage = ctx->d_stage();
+    for (int k = 0; k < n_domains; ++k) {
+        DomainHost& h = ctx->dom[k];
+        const lbm_domain_desc& d = domains[k];
+        const size_t n = h.n;
+        const int dim = d.lattice == LBM_D2Q9 ? 2 : 1;
+        double* f = stage;
+        if (d.f_init) {
+            e = hipMemcpyAsync(f, d.f_init, n * h.q * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+        } else {
+            double* rho = stage + size_t(h.q) * ctx->lay.max_n;
+            double* u = rho + ctx->lay.max_n;
+            std::vector<double> r(n, d.rho0), uu(n * dim, 0.0);
+            if (d.rho_init) std::memcpy(r.data(), d.rho_init, n * sizeof(double));
+            if (d.u_init) std::memcpy(uu.data(), d.u_init, n * dim * sizeof(double));
+            e = hipMemcpyAsync(rho, r.data(), n * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(u, uu.data(), n * dim * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess) e = launch_init_f(d.lattice, d.qe, rho, u, f, d.nx, d.ny, ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        }
+        if (e == hipSuccess)
+            e = launch_scatter(ctx->storage, d.lattice, d.bc, f, ctx->ws + h.off_buf[0], h.plane, d.nx, d.ny, h.shift,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("init: ") + hipGetErrorString(e)));
+    }
+    rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run->tile_x, run->tile_h) : set_tiles(ctx, kThreads - 2, 1);
+    if (rc) {
+        g_err = ctx->err;
+        return bail(rc);
+    }
+    // clean counters and stats after tuning launches
+    rc = reset_counters(ctx);
+    for (auto& h : ctx->dom)
+        if (!rc && hipMemsetAsync(ctx->ws + h.off_stats, 0, (kNStat + 1) * sizeof(double), ctx->stream) != hipSuccess)
+            rc = fail(ctx, LBM_EDEVICE, "hipMemsetAsync stats");
+    if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(ctx, LBM_EDEVICE, "sync after create");
+    if (rc) {
+        g_err = ctx->err;
+        return bail(rc);
+    }
+    *out = ctx;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* ctx, int64_t n_steps)
+{
+    if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
+    if (n_steps < 0) return fail(ctx, LBM_EINVAL, "n_steps < 0");
+    const bool use_graph = !(ctx->flags & LBM_RUN_NO_GRAPH);
+    int64_t since_check = 0;
+    while (n_steps > 0) {
+        int rc;
+        int64_t done;
+        const int parity = int(ctx->steps_done % 2);
+        if (use_graph && n_steps >= ctx->graph_chunk) {
+            if (!ctx->graph[parity] && (rc = capture(ctx, parity))) return rc;
+            HIP_TRY(ctx, hipGraphLaunch(ctx->graph[parity], ctx->stream));
+            done = ctx->graph_chunk;
+        } else {
+            if ((rc = launch_one(ctx, parity))) return rc;
+            done = 1;
+        }
+        ctx->steps_done += done;
+        n_steps -= done;
+        since_check += done;
+        if (ctx->stats_every > 0 && (since_check >= ctx->stats_every || n_steps == 0)) {
+            since_check = 0;
+            for (size_t d = 0; d < ctx->dom.size(); ++d) {
+                lbm_entropy_stats_t s;
+                s.struct_size = sizeof(s);
+                if ((rc = read_stats(ctx, int32_t(d), &s))) return rc;
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_synchronize(lbm_ctx* ctx)
+{
+    if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+int lbm_entropy_stats(lbm_ctx* ctx, int32_t domain, lbm_entropy_stats_t* out)
+{
+    int rc = check_domain(ctx, domain);
+    if (rc) return rc;
+    if (!out) return fail(ctx, LBM_EINVAL, "out is NULL");
+    return read_stats(ctx, domain, out);
+}
+
+static int gather_state(lbm_ctx* ctx, int32_t d, double* f, double* rho, double* u)
+{
+    const DomainHost& h = ctx->dom[d];
+    const size_t n = h.n;
+    const int dim = h.d.lattice == LBM_D2Q9 ? 2 : 1;
+    double* sf = ctx->d_stage();
+    double* sr = sf + size_t(h.q) * ctx->lay.max_n;
+    double* su = sr + ctx->lay.max_n;
+    const int parity = int(ctx->steps_done % 2);
+    hipError_t e = launch_gather(ctx->storage, h.d.lattice, h.d.bc, ctx->ws + h.off_buf[parity], h.plane, sf, h.d.nx,
+                                 h.d.ny, h.shift, f != nullptr, rho ? sr : nullptr, u ? su : nullptr, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("gather: ") + hipGetErrorString(e));
+    if (f) HIP_TRY(ctx, hipMemcpyAsync(f, sf, n * h.q * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (rho) HIP_TRY(ctx, hipMemcpyAsync(rho, sr, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (u) HIP_TRY(ctx, hipMemcpyAsync(u, su, n * dim * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* ctx, int32_t domain, double* rho, double* u)
+{
+    int rc = check_domain(ctx, domain);
+    if (rc) return rc;
+    if (!rho && !u) return LBM_OK;
+    return gather_state(ctx, domain, nullptr, rho, u);
+}
+
+int lbm_get_populations(lbm_ctx* ctx, int32_t domain, double* f)
+{
+    int rc = check_domain(ctx, domain);
+    if (rc) return rc;
+    if (!f) return fail(ctx, LBM_EINVAL, "f is NULL");
+    return gather_state(ctx, domain, f, nullptr, nullptr);
+}
+
+int lbm_set_populations(lbm_ctx* ctx, int32_t domain, const double* f)
+{
+    int rc = check_domain(ctx, domain);
+    if (rc) return rc;
+    if (!f) return fail(ctx, LBM_EINVAL, "f is NULL");
+    const DomainHost& h = ctx->dom[domain];
+    for (size_t s = 0; s < h.n * h.q; ++s)
+        if (!std::isfinite(f[s])) return fail(ctx, LBM_EINVAL, "f has non-finite values");
+    double* sf = ctx->d_stage();
+    const int parity = int(ctx->steps_done % 2);
+    HIP_TRY(ctx, hipMemcpyAsync(sf, f, h.n * h.q * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    hipError_t e = launch_scatter(ctx->storage, h.d.lattice, h.d.bc, sf, ctx->ws + h.off_buf[parity], h.plane, h.d.nx,
+                                  h.d.ny, h.shift, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("scatter: ") + hipGetErrorString(e));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+int lbm_limiter_mask(lbm_ctx* ctx, int32_t domain, uint8_t* mask, double* dS)
+{
+    int rc = check_domain(ctx, domain);
+    if (rc) return rc;
+    if (!(ctx->flags & LBM_RUN_RECORD)) return fail(ctx, LBM_EINVAL, "context was created without LBM_RUN_RECORD");
+    const DomainHost& h = ctx->dom[domain];
+    if (mask) HIP_TRY(ctx, hipMemcpyAsync(mask, ctx->ws + h.off_mask, h.n, hipMemcpyDeviceToHost, ctx->stream));
+    if (dS) HIP_TRY(ctx, hipMemcpyAsync(dS, ctx->ws + h.off_ds, h.n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
+}
+
+int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples, int64_t* n_written)
+{
+    int rc = check_domain(ctx, domain);
+    if (rc) return rc;
+    if (!n_written || (max_samples > 0 && !uv) || max_samples < 0) return fail(ctx, LBM_EINVAL, "bad probe buffers");
+    *n_written = 0;
+    const DomainHost& h = ctx->dom[domain];
+    if (h.d.probe_x < 0) return fail(ctx, LBM_EINVAL, "domain has no probe");
+    const int64_t cap = ctx->probe_cap;
+    const int64_t avail = std::min<int64_t>(ctx->steps_done, cap);
+    const int64_t take = std::min<int64_t>(avail, max_samples);
+    if (take == 0) return LBM_OK;
+    std::vector<float> ring(size_t(cap) * 2);
+    HIP_TRY(ctx, hipMemcpyAsync(ring.data(), ctx->ws + h.off_probe, ring.size() * sizeof(float), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t first = ctx->steps_done - take;
+    for (int64_t k = 0; k < take; ++k) {
+        const int64_t slot = (first + k) % cap;
+        uv[2 * k] = ring[2 * slot];
+        uv[2 * k + 1] = ring[2 * slot + 1];
+    }
+    *n_written = take;
+    return LBM_OK;
+}
+
+int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h)
+{
+    if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
+    if (tile_x) *tile_x = ctx->tx;
+    if (tile_y) *tile_y = ctx->ty;
+    if (tile_h) *tile_h = ctx->th;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) { release(ctx); }
+
+}  // extern "C"

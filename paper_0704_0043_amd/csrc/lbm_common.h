@@ -1,0 +1,91 @@
+// Structures shared by the host runtime (lbm.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum { kD1Q3 = 1, kD2Q9 = 2 };
+enum { kPoly = 0, kEntropic = 1 };
+enum { kExact = 0, kQuad = 1 };
+enum { kPeriodic = 0, kCavity = 1, kTube = 2 };
+enum { kLimTrim = 1, kLimMedian = 2 };
+enum { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8 };
+enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2 };
+
+constexpr int kThreads = 256;      // workgroup size of the step kernels
+constexpr int kMaxTileH = 510;     // rows per 2-D tile (halo buffer bound)
+constexpr int kNStat = 13;         // FP64 values per tile partial
+
+// partial / stats slot layout (FP64 each)
+enum {
+    kSMass = 0,   // sum of rho - shift (the shift is added back on the host)
+    kSJx, kSJy,
+    kSDpre, kSDpost, kSMax, kSLim, kSEnt,
+    kSTrim, kSFilt, kSNonpos, kSNonfin, kSFluid
+};
+
+// Per-domain parameters, device visible.  Pointers are device pointers.
+struct DomainDev {
+    void* buf[2];           // population planes (storage type), A and B
+    long long plane;        // elements per population plane
+    int nx, ny;
+    double c;               // 2 beta - 1
+    double shift;           // rho0 for shifted storage, 0 for FP64
+    double delta_trim, delta_median;
+    double rho0, lid_ux;
+    int limiter, trim_mode, median_mode;
+    int probe_x, probe_y, probe_cap;
+    float* probe;           // [probe_cap][2]
+    unsigned char* mask;    // [ny*nx] when recording
+    double* dS;             // [ny*nx] when recording
+    int tile_first, tile_count;   // this domain's range in the tile table
+    double* stats;          // [kNStat + 1]: last finalised sums, then the step index
+};
+
+constexpr int kXcds = 8;   // MI355X: 8 accelerator dies, each with its own L2
+
+// Workgroup b is dispatched to XCD b % 8.  Tiles are numbered in spatial
+// order (domain, row chunk, column strip); XCD x takes one contiguous range
+// of that order so neighbouring tiles share an L2.  This maps a block id to
+// its spatial tile index (a bijection on [0, T)).
+__host__ __device__ inline int xcd_spatial(int b, int T)
+{
+    const int x = b % kXcds, j = b / kXcds;
+    const int q = T / kXcds, r = T % kXcds;
+    return x * q + (x < r ? x : r) + j;
+}
+
+// one work item: a strip of columns [x0, x0 + width) and rows [y0, y1)
+struct Tile {
+    int domain, x0, y0, y1;
+};
+
+struct StepArgs {
+    const DomainDev* dom;
+    const Tile* tiles;      // indexed by blockIdx.x (XCD-aware order)
+    int ntiles;             // grid has ntiles + 1 blocks; the last one reduces
+    int ndomains;
+    int parity;             // read buf[parity], write buf[1 - parity]
+    unsigned flags;
+    double* partials;       // [2][ntiles][kNStat], indexed by spatial tile
+    long long* counter;     // [2] step index by parity
+    int tile_w;             // strip width in columns (threads along x)
+};
+
+// Launchers (one per storage type / lattice), defined in the .hip files.
+hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int tx, int ty,
+                         int tile_h, hipStream_t s);
+hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, hipStream_t s);
+hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);
+hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u, double* f, int nx, int ny,
+                         hipStream_t s);
+hipError_t launch_scatter(int storage, int lattice, int bc, const double* f, void* buf, long long plane, int nx,
+                          int ny, double shift, hipStream_t s);
+hipError_t launch_gather(int storage, int lattice, int bc, const void* buf, long long plane, double* f, int nx,
+                         int ny, double shift, int want_f, double* rho, double* u, hipStream_t s);
+
+}  // namespace lbm

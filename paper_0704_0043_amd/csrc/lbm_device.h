@@ -1,0 +1,470 @@
+// Device building blocks of the limited LBGK step (gfx950).
+//
+// Arithmetic is FP64 for FP64 storage and FP32 for the shifted FP32/FP16/BF16
+// storage.  Populations are handled in shift form g_i = f_i - w_i * shift
+// (shift = rho0 for reduced storage, 0 for FP64), so that the equilibrium and
+// the nonequilibrium part are computed without cancellation:
+//   rho = shift + sum g_i,   g*_i = w_i (sum g + rho E_i(u)),   d_i = g_i - g*_i
+// where E_i = f*_i / (rho w_i) - 1 is the "equilibrium excess" of the
+// quasiequilibria of Sec. 4.1.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbm_common.h"
+
+namespace lbm {
+
+// ---- lattices (Sec. 4.1) ----------------------------------------------------
+// D2Q9 order: rest, E, N, W, S, NE, NW, SW, SE.  D1Q3 order: rest, v=-1, v=+1.
+template <int LAT>
+struct Lat;
+
+template <>
+struct Lat<kD2Q9> {
+    static constexpr int Q = 9;
+    __host__ __device__ static constexpr int vx(int i)
+    {
+        return (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0;
+    }
+    __host__ __device__ static constexpr int vy(int i)
+    {
+        return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0;
+    }
+    __host__ __device__ static constexpr int opp(int i)
+    {
+        return i == 0 ? 0 : (i <= 4 ? (i + 1) % 4 + 1 : (i - 3) % 4 + 5);
+    }
+    // weights of the rest state (polynomial equilibrium at u = 0)
+    __host__ __device__ static constexpr double w(int i)
+    {
+        return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+    // W_i of the entropy S = -sum f ln(f/W) (same numbers for D2Q9)
+    __host__ __device__ static constexpr double went(int i) { return w(i); }
+};
+
+template <>
+struct Lat<kD1Q3> {
+    static constexpr int Q = 3;
+    __host__ __device__ static constexpr int vx(int i) { return i == 0 ? 0 : (i == 1 ? -1 : 1); }
+    __host__ __device__ static constexpr int vy(int) { return 0; }
+    __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : 3 - i; }
+    __host__ __device__ static constexpr double w(int i) { return i == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+    // H = f1 log(f1/4) + f2 log f2 + f3 log f3
+    __host__ __device__ static constexpr double went(int i) { return i == 0 ? 4.0 : 1.0; }
+};
+
+// ---- storage ---------------------------------------------------------------
+template <class T>
+struct Store;
+
+template <>
+struct Store<double> {
+    using A = double;
+    __device__ static A ld(const double* p) { return *p; }
+    __device__ static void st(double* p, A v) { *p = v; }
+};
+template <>
+struct Store<float> {
+    using A = float;
+    __device__ static A ld(const float* p) { return *p; }
+    __device__ static void st(float* p, A v) { *p = v; }
+};
+template <>
+struct Store<__half> {
+    using A = float;
+    __device__ static A ld(const __half* p) { return __half2float(*p); }
+    __device__ static void st(__half* p, A v) { *p = __float2half_rn(v); }
+};
+template <>
+struct Store<__hip_bfloat16> {
+    using A = float;
+    __device__ static A ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+    __device__ static void st(__hip_bfloat16* p, A v) { *p = __float2bfloat16(v); }
+};
+
+// ---- arithmetic helpers ------------------------------------------------------
+// FP64: IEEE division and square root.  FP32: the hardware reciprocal and
+// square root (about 1 ulp), well inside the FP32 error budget.
+__device__ inline double rcp(double x) { return 1.0 / x; }
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double sqrt_(double x) { return sqrt(x); }
+__device__ inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double log1p_(double x) { return log1p(x); }
+__device__ inline float log1p_(float x) { return log1pf(x); }
+__device__ inline double log_(double x) { return log(x); }
+__device__ inline float log_(float x) { return logf(x); }
+
+__device__ inline float med3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }
+__device__ inline double med3(double a, double b, double c) { return fmax(fmin(a, b), fmin(fmax(a, b), c)); }
+template <class A>
+__device__ inline A min3(A a, A b, A c) { return fmin(fmin(a, b), c); }
+template <class A>
+__device__ inline A max3(A a, A b, A c) { return fmax(fmax(a, b), c); }
+
+// Median of a 3x3 block: sort each row (min / med / max), then the median of
+// all nine is med3(max of row minima, med of row medians, min of row maxima).
+template <class A>
+__device__ inline A median9(A a0, A a1, A a2, A a3, A a4, A a5, A a6, A a7, A a8)
+{
+    A lo = max3(min3(a0, a1, a2), min3(a3, a4, a5), min3(a6, a7, a8));
+    A mi = med3(med3(a0, a1, a2), med3(a3, a4, a5), med3(a6, a7, a8));
+    A hi = min3(max3(a0, a1, a2), max3(a3, a4, a5), max3(a6, a7, a8));
+    return med3(lo, mi, hi);
+}
+
+// h(x) = (1 + x) ln(1 + x) - x, so that sum f ln(f/f*) = sum f* h((f - f*)/f*)
+// when f and f* share their moments (eq. DelS).  Near x = 0 the closed form
+// cancels; there the alternating series x^2 sum_k (-x)^k / ((k+1)(k+2)) is
+// summed in Horner form (truncation below 1e-17 relative for |x| <= 0.1 in
+// FP64 and 2e-8 for |x| <= 0.5 in FP32).
+__device__ inline double hkern(double x)
+{
+    if (fabs(x) <= 0.1) {
+        double p = 1.0 / (16.0 * 17.0);
+#pragma unroll
+        for (int k = 14; k >= 0; --k) p = 1.0 / ((k + 1.0) * (k + 2.0)) - x * p;
+        return x * x * p;
+    }
+    return (1.0 + x) * log1p(x) - x;
+}
+__device__ inline float hkern(float x)
+{
+    if (fabsf(x) <= 0.5f) {
+        float p = 1.0f / (22.0f * 23.0f);
+#pragma unroll
+        for (int k = 20; k >= 0; --k) p = 1.0f / ((k + 1.0f) * (k + 2.0f)) - x * p;
+        return x * x * p;
+    }
+    return (1.0f + x) * log1pf(x) - x;
+}
+
+// ---- quasiequilibria, excess form -------------------------------------------
+// One axis of the entropic equilibrium: f*(v) / (rho w_v) = A B^v with
+// A = 2 - s, B = (2u + s)/(1 - u), s = sqrt(1 + 3u^2) (eq. maxwellian; the
+// D1Q3 equilibrium of eq. entropiceq1d is the same factor).  Returned as
+// X_v = A B^v - 1 for v = 0, -1, +1 using s - 1 = 3u^2/(1 + s) and
+// 1/B = (s - 2u)/(1 + u).
+template <class A>
+__device__ inline void axis_excess(A u, A& x0, A& xm, A& xp)
+{
+    A s = sqrt_(A(1) + A(3) * u * u);
+    A q = A(3) * u * u * rcp(A(1) + s);   // s - 1
+    A a = -q;                               // A - 1
+    A bp = (A(3) * u + q) * rcp(A(1) - u);  // B - 1
+    A bm = (q - A(3) * u) * rcp(A(1) + u);  // 1/B - 1
+    x0 = a;
+    xm = a + bm + a * bm;
+    xp = a + bp + a * bp;
+}
+
+template <int LAT, int QE, class A>
+__device__ inline void eq_excess(A ux, A uy, A (&E)[Lat<LAT>::Q])
+{
+    using L = Lat<LAT>;
+    if constexpr (QE == kPoly) {
+        // eqs. (polyeq1d), (polyeq2d): 1 + 3 c + 9 c^2 / 2 - 3 u^2 / 2, c = v.u
+        A base = A(-1.5) * (ux * ux + uy * uy);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            A cu = A(L::vx(i)) * ux + A(L::vy(i)) * uy;
+            E[i] = base + cu * (A(3) + A(4.5) * cu);
+        }
+    } else {
+        A x0, xm, xp, y0 = 0, ym = 0, yp = 0;
+        axis_excess(ux, x0, xm, xp);
+        if constexpr (LAT == kD2Q9) axis_excess(uy, y0, ym, yp);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            A X = L::vx(i) == 0 ? x0 : (L::vx(i) > 0 ? xp : xm);
+            if constexpr (LAT == kD2Q9) {
+                A Y = L::vy(i) == 0 ? y0 : (L::vy(i) > 0 ? yp : ym);
+                E[i] = X + Y + X * Y;
+            } else {
+                E[i] = X;
+            }
+        }
+    }
+}
+
+// ---- one site: moments, f*, collision, nonequilibrium entropy ---------------
+template <int LAT, class A>
+struct SiteState {
+    static constexpr int Q = Lat<LAT>::Q;
+    A gs[Q];      // shifted equilibrium g*_i = f*_i - w_i shift
+    A d[Q];       // nonequilibrium part g_i - g*_i = f_i - f*_i
+    A dpost;      // Delta S(f'), +inf when undefined
+};
+
+struct SiteScalars {
+    double dr, jx, jy;   // moments (FP64 for the reductions)
+    double dpre;
+    float ux, uy;
+    bool nonpos;
+};
+
+template <int LAT, int QE, int DS, class A>
+__device__ inline void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, SiteState<LAT, A>& o,
+                                    SiteScalars& sc, bool want_pre)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    A dr = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        dr += g[i];
+        if (L::vx(i) > 0) jx += g[i];
+        if (L::vx(i) < 0) jx -= g[i];
+        if (L::vy(i) > 0) jy += g[i];
+        if (L::vy(i) < 0) jy -= g[i];
+    }
+    A rho = shift + dr;              // eq. (macro_dis)
+    A inv = rcp(rho);
+    A ux = jx * inv, uy = jy * inv;
+    A E[Q];
+    eq_excess<LAT, QE>(ux, uy, E);
+    A fs[Q];
+    bool fs_ok = true, pre_ok = true, post_ok = true;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        o.gs[i] = A(L::w(i)) * (dr + rho * E[i]);
+        fs[i] = A(L::w(i)) * shift + o.gs[i];
+        o.d[i] = g[i] - o.gs[i];
+        fs_ok &= fs[i] > A(0);
+        pre_ok &= (g[i] + A(L::w(i)) * shift) > A(0);
+        post_ok &= (fs[i] - c * o.d[i]) > A(0);
+    }
+    A dpre = 0, dpost = 0;
+    if constexpr (DS == kQuad) {
+        // sum (f - f*)^2 / (2 f*); after collision f' - f* = -c d (eq. collLBGK)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dpre += o.d[i] * o.d[i] * rcp(fs[i]);
+        dpre *= A(0.5);
+        dpost = c * c * dpre;
+        pre_ok = post_ok = true;
+    } else {
+        A x[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) x[i] = o.d[i] * rcp(fs[i]);
+        if (want_pre) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dpre += fs[i] * hkern(x[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dpost += fs[i] * hkern(-c * x[i]);
+    }
+    const A inf = A(__builtin_huge_val());
+    if (!fs_ok) pre_ok = post_ok = false;
+    o.dpost = post_ok ? dpost : inf;
+    sc.dpre = pre_ok ? double(dpre) : double(inf);
+    sc.nonpos = !(pre_ok && post_ok);
+    // non-finite moments or velocity (e.g. rho = 0) propagate as NaN
+    if (!(isfinite(rho) && isfinite(ux) && isfinite(uy))) {
+        o.dpost = A(__builtin_nan(""));
+        sc.dpre = __builtin_nan("");
+        sc.nonpos = false;
+    }
+    sc.dr = double(dr);
+    sc.jx = double(jx);
+    sc.jy = double(jy);
+    sc.ux = float(ux);
+    sc.uy = float(uy);
+}
+
+// Delta S of f* + s (f' - f*) = f* - s c d, used for the limiter's entropy
+// production (eq. LimEntLim).
+template <int LAT, int DS, class A>
+__device__ inline A delta_s_scaled(const SiteState<LAT, A>& o, A shift, A c, A s)
+{
+    using L = Lat<LAT>;
+    if constexpr (DS == kQuad) {
+        return s * s * o.dpost;
+    } else {
+        A sum = 0;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            A fs = A(L::w(i)) * shift + o.gs[i];
+            sum += fs * hkern(-s * c * o.d[i] * rcp(fs));
+        }
+        return sum;
+    }
+}
+
+// S(f) = -sum f ln(f/W) (Sec. 4.3.1), NaN when a population is not positive
+template <int LAT, class A>
+__device__ inline double entropy_site(const A (&g)[Lat<LAT>::Q], A shift)
+{
+    using L = Lat<LAT>;
+    A s = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        A f = g[i] + A(L::w(i)) * shift;
+        if (!(f > A(0))) return __builtin_nan("");
+        s -= f * log_(f * A(1.0 / L::went(i)));
+    }
+    return double(s);
+}
+
+// ---- limiter -----------------------------------------------------------------
+// phi for one fluid site (eq. LimGenF): trimming (eq. entrHom / Ehrenfests'
+// step) and the median filter (Sec. 3.5); both on -> the smaller phi.
+template <class A>
+__device__ inline A limiter_phi(A dpost, bool has_med, A med, const DomainDev& D, unsigned& mask)
+{
+    A phi = A(1);
+    if (D.limiter & kLimTrim) {
+        A t = A(D.delta_trim);
+        if (dpost > t) {
+            mask |= kMaskTrim;
+            A p = D.trim_mode ? A(0) : sqrt_(t * rcp(dpost));
+            phi = fmin(phi, p);
+        }
+    }
+    if ((D.limiter & kLimMedian) && has_med) {
+        A dm = A(D.delta_median);
+        bool hit;
+        A t;
+        if (D.median_mode) {
+            hit = dpost > dm && dpost > med;
+            t = med;
+        } else {
+            t = fmax(med, dm);
+            hit = dpost > t;
+        }
+        if (hit) {
+            mask |= kMaskMedian;
+            phi = fmin(phi, sqrt_(t * rcp(dpost)));
+        }
+    }
+    return phi;
+}
+
+// ---- statistics ----------------------------------------------------------------
+struct Acc {
+    double mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
+    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0;
+
+    __device__ void moments(const SiteScalars& s)
+    {
+        mass += s.dr;
+        jx += s.jx;
+        jy += s.jy;
+        if (!(isfinite(s.dr) && isfinite(s.jx) && isfinite(s.jy))) ++nonfin;
+    }
+    template <class A>
+    __device__ void fluid_site(const SiteScalars& s, A dpost)
+    {
+        ++fluid;
+        if (s.nonpos) ++nonpos;
+        if (isfinite(s.dpre)) dpre += s.dpre;
+        double dp = double(dpost);
+        if (isfinite(dp)) {
+            dpost += dp;
+            maxd = fmax(maxd, dp);
+        }
+    }
+};
+
+// Deterministic workgroup reduction of the accumulators into one partial
+// (fixed butterfly inside each wave, then waves in order).
+__device__ inline void store_partial(const Acc& acc, double* out, double* lds /* [4 * kNStat] */)
+{
+    double v[kNStat] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent,
+                        double(acc.trim), double(acc.filt), double(acc.nonpos), double(acc.nonfin),
+                        double(acc.fluid)};
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) {
+            double o = __shfl_xor(v[k], off, 64);
+            v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) lds[wave * kNStat + k] = v[k];
+    }
+    __syncthreads();
+    if (tid < kNStat) {
+        const int nw = (blockDim.x * blockDim.y) >> 6;
+        double s = lds[tid];
+        for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
+        out[tid] = s;
+    }
+}
+
+// Reduce the partials of the step that ran with `parity` into each domain's
+// stats slot (fixed order per domain).  Run by one workgroup.
+constexpr int kSmallDomainTiles = 32;
+
+__device__ inline void reduce_partials(const StepArgs& a, int parity, long long step, double* lds)
+{
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthr = blockDim.x * blockDim.y;
+    const double* part = a.partials + (long long)parity * a.ntiles * kNStat;
+    // domains with few tiles: one thread each, tiles summed in order
+    for (int d = tid; d < a.ndomains; d += nthr) {
+        const DomainDev& D = a.dom[d];
+        if (D.tile_count > kSmallDomainTiles) continue;
+        double v[kNStat];
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) v[k] = 0;
+        for (int t = 0; t < D.tile_count; ++t) {
+            const double* p = part + (long long)(D.tile_first + t) * kNStat;
+#pragma unroll
+            for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) D.stats[k] = v[k];
+        D.stats[kNStat] = double(step);
+    }
+    // large domains: the whole workgroup, fixed slices then a fixed tree
+    for (int d = 0; d < a.ndomains; ++d) {
+        const DomainDev& D = a.dom[d];
+        if (D.tile_count <= kSmallDomainTiles) continue;
+        double v[kNStat];
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) v[k] = 0;
+        for (int t = tid; t < D.tile_count; t += nthr) {
+            const double* p = part + (long long)(D.tile_first + t) * kNStat;
+#pragma unroll
+            for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < kNStat; ++k) {
+                double o = __shfl_xor(v[k], off, 64);
+                v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
+            }
+        }
+        const int wave = tid >> 6, lane = tid & 63;
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kNStat; ++k) lds[wave * kNStat + k] = v[k];
+        }
+        __syncthreads();
+        if (tid < kNStat) {
+            const int nw = nthr >> 6;
+            double s = lds[tid];
+            for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
+            D.stats[tid] = s;
+        }
+        if (tid == 0) D.stats[kNStat] = double(step);
+        __syncthreads();
+    }
+}
+
+__host__ __device__ inline int wrapi(int a, int n)
+{
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+}  // namespace lbm

@@ -1,0 +1,99 @@
+"""Helpers of the GPU parity tests: run the same seeded input through the HIP
+library (via the C ABI binding) and through the FP64 oracle, and compare."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+
+def require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+
+
+def lbm():
+    from paper_0704_0043_amd import lbm as L
+    L.lib()                      # fails loudly when the library is not built
+    return L
+
+
+def orc():
+    from oracle import oracle
+    oracle.build()
+    return oracle
+
+
+def oracle_params(d, entropy=False):
+    o = orc()
+    return o.make_params(lattice=d.lattice, nx=d.nx, ny=d.ny, beta=d.beta, qe=d.qe, ds_form=d.ds_form,
+                         limiter=d.limiter, trim_mode=d.trim_mode, median_mode=d.median_mode, bc=d.bc,
+                         delta_trim=d.delta_trim, delta_median=d.delta_median, rho0=d.rho0, lid_ux=d.lid_ux,
+                         entropy=entropy)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Pair:
+    """GPU and oracle results after `steps` steps from the same state."""
+
+    def __init__(self, dom, f0, steps=1, storage=0, tile=None, flags=None, entropy=False):
+        L = lbm()
+        o = orc()
+        say(f"[case] lattice={dom.lattice} n={dom.nx}x{dom.ny} bc={dom.bc} qe={dom.qe} ds={dom.ds_form} "
+            f"lim={dom.limiter} modes={dom.trim_mode}/{dom.median_mode} storage={storage} steps={steps} tile={tile}")
+        dom.f_init = np.ascontiguousarray(f0)
+        fl = L.LBM_RUN_RECORD | (L.LBM_RUN_ENTROPY if entropy else 0) if flags is None else flags
+        run = L.Run(storage=storage, flags=fl)
+        if tile:
+            run.tile_x, run.tile_y, run.tile_h = tile[0], 256 // tile[0], tile[1]
+        with L.lbm_create([dom], run) as ctx:
+            self.tile = L.lbm_tile_config(ctx)
+            L.lbm_step(ctx, steps)
+            self.f = L.lbm_get_populations(ctx)
+            self.stats = L.lbm_entropy_stats(ctx, allow_unstable=True)
+            if fl & L.LBM_RUN_RECORD:
+                self.mask, self.ds = L.lbm_limiter_mask(ctx)
+            self.rho, self.u = L.lbm_moments(ctx)
+        p = oracle_params(dom, entropy)
+        self.fo = np.ascontiguousarray(f0, dtype=np.float64).copy()
+        st, self.mo, self.dso = o.step(p, self.fo, steps, record=True)
+        self.so = st.as_dict()
+        dom.f_init = None
+
+
+def assert_masks_equal(pr):
+    mism = np.nonzero(pr.mask != pr.mo)
+    if len(mism[0]):
+        k = (mism[0][0], mism[1][0])
+        raise AssertionError(f"{len(mism[0])} mask mismatches; first at {k}: gpu {pr.mask[k]} oracle {pr.mo[k]} "
+                             f"dS gpu {pr.ds[k]!r} oracle {pr.dso[k]!r}")
+
+
+def assert_ds_close(pr, rtol):
+    a, b = pr.ds, pr.dso
+    fin = np.isfinite(b)
+    assert np.array_equal(np.isfinite(a), fin)
+    assert np.array_equal(np.isinf(a), np.isinf(b))
+    scale = np.maximum(np.abs(b[fin]), 1e-300)
+    err = np.abs(a[fin] - b[fin]) / scale
+    assert err.max(initial=0.0) <= rtol, f"dS rel err {err.max():.3e}"
+
+
+def assert_stats_close(pr, rtol=1e-11, counts=True):
+    g, o = pr.stats, pr.so
+    assert g["mass"] == pytest.approx(o["mass"], rel=rtol)
+    m = abs(o["mass"])
+    assert abs(g["mom_x"] - o["mom_x"]) <= rtol * m
+    assert abs(g["mom_y"] - o["mom_y"]) <= rtol * m
+    for k in ("sum_dS_pre", "sum_dS_post", "max_dS"):
+        assert g[k] == pytest.approx(o[k], rel=rtol, abs=1e-300), k
+    assert abs(g["limiter_production"] - o["limiter_production"]) <= rtol * max(o["sum_dS_post"], 1e-300) * 10
+    if counts:
+        for k in ("n_trimmed", "n_filtered", "n_nonpositive", "n_nonfinite", "n_fluid"):
+            assert g[k] == o[k], (k, g[k], o[k])

@@ -1,0 +1,116 @@
+"""The C ABI library loads, exports every symbol include/lbm.h declares, and
+its struct layouts match the Python binding.  No GPU is touched: only
+host-side entry points (argument validation, sizes, strings) are called."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0704_0043_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_0704_0043_amd import build
+        build.build()
+    return lbm
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"LBM_API\s+[\w\s\*]+?\b(lbm_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lbm_create", "lbm_step", "lbm_moments", "lbm_entropy_stats", "lbm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(L.SIGNATURES)
+
+
+def test_only_the_c_abi_is_exported(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True)
+    text_syms = {ln.split()[-1] for ln in out.stdout.splitlines() if " T " in ln}
+    assert text_syms == set(declared_functions())
+
+
+def c_layout():
+    """sizeof/offsetof of the ABI structs as seen by a C compiler."""
+    probe = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "lbm.h"
+#define OFF(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("lbm_domain_desc %zu\n", sizeof(lbm_domain_desc));
+  printf("lbm_run_desc %zu\n", sizeof(lbm_run_desc));
+  printf("lbm_entropy_stats_t %zu\n", sizeof(lbm_entropy_stats_t));
+  OFF(lbm_domain_desc, beta); OFF(lbm_domain_desc, delta_trim); OFF(lbm_domain_desc, rho_init);
+  OFF(lbm_domain_desc, f_init); OFF(lbm_domain_desc, probe_y);
+  OFF(lbm_run_desc, flags); OFF(lbm_run_desc, stream); OFF(lbm_run_desc, workspace_bytes);
+  OFF(lbm_entropy_stats_t, step); OFF(lbm_entropy_stats_t, total_entropy); OFF(lbm_entropy_stats_t, n_fluid);
+  return 0;
+}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(probe)
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    return dict(ln.rsplit(" ", 1) for ln in out.strip().splitlines())
+
+
+def test_struct_layouts_match_binding(L):
+    lay = {k: int(v) for k, v in c_layout().items()}
+    for cls in (L.lbm_domain_desc, L.lbm_run_desc, L.lbm_entropy_stats_t):
+        assert ctypes.sizeof(cls) == lay[cls.__name__], cls.__name__
+    for key, val in lay.items():
+        if "." in key:
+            struct, fld = key.split(".")
+            assert getattr(getattr(L, struct), fld).offset == val, key
+
+
+def test_host_only_entry_points(L):
+    assert L.lbm_abi_version() == 1
+    assert L.lbm_beta_from_nu(1e-4) == pytest.approx(1 / (6e-4 + 1), rel=1e-15)
+    assert "invalid" in L.lbm_strerror(L.LBM_EINVAL)
+    n = L.lbm_workspace_bytes([L.Domain(nx=128, ny=64)], L.Run(storage=L.LBM_F32))
+    # two FP32 population buffers of 9 planes at least
+    assert n >= 2 * 9 * 128 * 64 * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(beta=1.5), dict(beta=-0.1), dict(delta_trim=-1.0), dict(delta_median=float("nan")),
+    dict(nx=0), dict(bc=1, nx=3, ny=10), dict(lattice=3), dict(lattice=1, bc=1),
+    dict(lattice=2, bc=2), dict(qe=7), dict(limiter=9), dict(rho0=0.0), dict(probe=(500, 1)),
+    dict(bc=1, nx=10, ny=10, probe=(0, 5)),
+])
+def test_invalid_descriptors_are_rejected_before_any_device_call(L, bad):
+    kw = dict(nx=32, ny=16)
+    kw.update(bad)
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_workspace_bytes([L.Domain(**kw)], L.Run())
+    assert e.value.code == L.LBM_EINVAL
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_create([L.Domain(**kw)], L.Run())
+    assert e.value.code == L.LBM_EINVAL
+
+
+def test_mixed_batches_are_rejected(L):
+    with pytest.raises(L.LbmError):
+        L.lbm_workspace_bytes([L.Domain(qe=0), L.Domain(qe=1)], L.Run())
+    with pytest.raises(L.LbmError):
+        L.lbm_workspace_bytes([L.Domain(), L.Domain()], L.Run(tile_x=96))

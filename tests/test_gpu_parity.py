@@ -1,0 +1,300 @@
+"""Parity of the HIP step (through the C ABI) with the FP64 oracle.
+
+FP64 storage: limiter masks bit-exact, Delta S' and populations to a few
+ulp, global sums to 1e-11.  Sizes span several tiles with ragged edges;
+tile shapes are both fixed (small, many tiles) and autotuned.
+"""
+import numpy as np
+import pytest
+
+from paper_0704_0043_amd import workloads as wl
+from tests.gpu_util import (Pair, assert_ds_close, assert_masks_equal, assert_stats_close, lbm, orc,
+                            require_gpu, say)
+
+pytestmark = pytest.mark.gpu
+
+D1Q3, D2Q9 = 1, 2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def dom2d(**kw):
+    L = lbm()
+    base = dict(lattice=D2Q9, nx=300, ny=70, beta=0.97, delta_trim=1e-4, delta_median=1e-5)
+    base.update(kw)
+    return L.Domain(**base)
+
+
+def fields_close(pr, rtol=1e-13):
+    scale = np.abs(pr.fo).max()
+    err = np.abs(pr.f - pr.fo).max() / scale
+    assert err <= rtol, f"population max rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("tile", [(64, 16), None])
+@pytest.mark.parametrize("limiter", [0, 1, 2, 3])
+@pytest.mark.parametrize("ds", [0, 1])
+@pytest.mark.parametrize("qe", [0, 1])
+def test_d2q9_periodic_single_step_fp64(qe, ds, limiter, tile):
+    f0 = wl.random_populations(9, 300, 70, seed=11 + qe + 2 * ds, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    pr = Pair(dom2d(qe=qe, ds_form=ds, limiter=limiter), f0, steps=1, storage=0, tile=tile)
+    assert_masks_equal(pr)
+    assert_ds_close(pr, 1e-12)
+    fields_close(pr)
+    assert_stats_close(pr)
+    if limiter & 1:
+        assert pr.so["n_trimmed"] > 0
+    if limiter & 2:
+        assert pr.so["n_filtered"] > 0
+
+
+@pytest.mark.parametrize("trim_mode,median_mode", [(1, 0), (0, 1), (1, 1)])
+def test_d2q9_limiter_modes_fp64(trim_mode, median_mode):
+    f0 = wl.random_populations(9, 130, 90, seed=5, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    pr = Pair(dom2d(nx=130, ny=90, qe=1, limiter=3, trim_mode=trim_mode, median_mode=median_mode,
+                    delta_trim=3e-4, delta_median=2e-5), f0, tile=(128, 32))
+    assert_masks_equal(pr)
+    assert_ds_close(pr, 1e-12)
+    fields_close(pr)
+    assert_stats_close(pr)
+
+
+@pytest.mark.parametrize("ds", [0, 1])
+def test_nonpositive_populations_fp64(ds):
+    """Sites with a negative population: Delta S = +inf in the exact form and
+    every enabled limiter returns the site to f*."""
+    f0 = wl.random_populations(9, 96, 40, seed=21, amp=0.05, spike_frac=0.05, spike_amp=0.4, negative_frac=0.02)
+    pr = Pair(dom2d(nx=96, ny=40, qe=0, ds_form=ds, limiter=3), f0, tile=(64, 16))
+    assert_masks_equal(pr)
+    assert_ds_close(pr, 1e-12)
+    fields_close(pr)
+    assert_stats_close(pr)
+    assert pr.so["n_nonpositive"] > 0
+
+
+@pytest.mark.parametrize("limiter", [0, 2, 3])
+@pytest.mark.parametrize("qe", [0, 1])
+def test_cavity_single_step_fp64(qe, limiter):
+    """100 x 100 cavity (the paper's grid): walls, lid and near-wall median stencils."""
+    L = lbm()
+    f0 = wl.random_populations(9, 100, 100, seed=31 + qe, rho0=2.7, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    d = L.Domain(lattice=D2Q9, nx=100, ny=100, beta=0.97087, qe=qe, limiter=limiter, bc=1, rho0=2.7, lid_ux=0.1,
+                 delta_trim=1e-4, delta_median=1e-5)
+    for tile in [(64, 16), None]:
+        pr = Pair(d, f0, tile=tile)
+        assert_masks_equal(pr)
+        assert_ds_close(pr, 1e-12)
+        fields_close(pr)
+        assert_stats_close(pr)
+
+
+@pytest.mark.parametrize("bc", [0, 2])
+@pytest.mark.parametrize("limiter", [0, 1, 2, 3])
+@pytest.mark.parametrize("ds", [0, 1])
+@pytest.mark.parametrize("qe", [0, 1])
+def test_d1q3_single_step_fp64(qe, ds, limiter, bc):
+    L = lbm()
+    f0 = wl.random_populations(3, 800, 1, seed=41 + qe + 2 * ds, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    d = L.Domain(lattice=D1Q3, nx=800, ny=1, beta=0.95, qe=qe, ds_form=ds, limiter=limiter, bc=bc,
+                 delta_trim=1e-4, delta_median=1e-5)
+    pr = Pair(d, f0)
+    assert_masks_equal(pr)
+    assert_ds_close(pr, 1e-12)
+    fields_close(pr)
+    assert_stats_close(pr)
+
+
+def test_shock_tube_config_fp64():
+    """D1Q3 800 sites, polynomial f*, nu = 1e-9, trimming delta = 1e-3, tube
+    ends, 400 steps from the 1:2 density step, FP64: the full small config."""
+    L = lbm()
+    o = orc()
+    rho, u = wl.shock_tube(800, 400)
+    d = L.Domain(lattice=D1Q3, nx=800, ny=1, beta=wl.beta_from_nu(1e-9), qe=0, ds_form=0, limiter=1, bc=2,
+                 delta_trim=1e-3)
+    p = o.make_params(lattice=1, nx=800, beta=d.beta, qe=0, limiter=1, delta_trim=1e-3, bc=2)
+    f0 = o.init_equilibrium(p, rho, u)
+    pr = Pair(d, f0, steps=400)
+    assert_masks_equal(pr)
+    fields_close(pr, rtol=1e-11)
+    assert_stats_close(pr, rtol=1e-9)
+
+
+@pytest.mark.parametrize("qe", [0, 1])
+def test_cavity_multistep_fp64(qe):
+    """100 x 100 cavity from rest, Re = 2000, median delta = 1e-3, 300 steps."""
+    L = lbm()
+    o = orc()
+    rho, u = wl.cavity_rest(100, rho0=2.7)
+    d = L.Domain(lattice=D2Q9, nx=100, ny=100, beta=wl.beta_from_nu(0.1 * 100 / 2000), qe=qe, limiter=2, bc=1,
+                 rho0=2.7, lid_ux=0.1, delta_median=1e-3)
+    f0 = o.init_equilibrium(o.make_params(lattice=2, nx=100, ny=100, qe=qe, bc=1), rho, u)
+    pr = Pair(d, f0, steps=300)
+    assert_masks_equal(pr)
+    fields_close(pr, rtol=1e-11)
+    assert_stats_close(pr, rtol=1e-10)
+
+
+def test_initial_equilibrium_and_moments_fp64():
+    """f(x, 0) = f*(rho, u) built on the device vs the oracle; lbm_moments."""
+    L = lbm()
+    o = orc()
+    for qe in (0, 1):
+        rho, u = wl.random_flow(77, 45, seed=3, umax=0.2)
+        d = L.Domain(lattice=D2Q9, nx=77, ny=45, qe=qe, rho_init=rho, u_init=u)
+        with L.lbm_create([d], L.Run(storage=0)) as ctx:
+            f = L.lbm_get_populations(ctx)
+            r, uu = L.lbm_moments(ctx)
+        fo = o.init_equilibrium(o.make_params(lattice=2, nx=77, ny=45, qe=qe), rho, u)
+        assert np.abs(f - fo).max() <= 4e-16 * np.abs(fo).max() * 8
+        ro, ux, uy = o.moments(2, fo)
+        assert np.allclose(r, ro, rtol=1e-15, atol=0)
+        assert np.allclose(uu[0], ux, rtol=1e-13, atol=1e-17) and np.allclose(uu[1], uy, rtol=1e-13, atol=1e-17)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_set_get_roundtrip_and_zero_steps(storage):
+    L = lbm()
+    f0 = wl.random_populations(9, 65, 33, seed=9)
+    d = L.Domain(lattice=D2Q9, nx=65, ny=33, bc=1, rho0=1.0, f_init=f0)
+    with L.lbm_create([d], L.Run(storage=storage)) as ctx:
+        g = L.lbm_get_populations(ctx)
+        L.lbm_step(ctx, 0)
+        assert np.array_equal(L.lbm_get_populations(ctx), g)
+        L.lbm_step(ctx, 3)
+        L.lbm_set_populations(ctx, f0)
+        h = L.lbm_get_populations(ctx)
+    if storage == 0:
+        assert np.array_equal(g, f0) and np.array_equal(h, f0)
+    else:
+        assert np.abs(g - f0).max() < 1e-7 and np.array_equal(g, h)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_tile_shapes_give_identical_fields(storage):
+    """Per-site arithmetic does not depend on the tiling (catches halo/ring races)."""
+    L = lbm()
+    f0 = wl.random_populations(9, 300, 70, seed=77, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    outs = []
+    for tile in [(64, 16), (128, 32), (256, 128), (256, 510), (64, 48)]:
+        d = dom2d(qe=1, ds_form=1 if storage else 0, limiter=3, f_init=f0)
+        run = L.Run(storage=storage, tile_x=tile[0], tile_y=256 // tile[0], tile_h=tile[1], flags=L.LBM_RUN_RECORD)
+        with L.lbm_create([d], run) as ctx:
+            L.lbm_step(ctx, 5)
+            outs.append((L.lbm_get_populations(ctx), L.lbm_limiter_mask(ctx)[0]))
+    for f, m in outs[1:]:
+        assert np.array_equal(f, outs[0][0])
+        assert np.array_equal(m, outs[0][1])
+
+
+def test_repeat_runs_are_bitwise_identical():
+    L = lbm()
+    f0 = wl.random_populations(9, 200, 120, seed=3, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    res = []
+    for _ in range(2):
+        d = dom2d(nx=200, ny=120, qe=0, ds_form=1, limiter=3, f_init=f0)
+        with L.lbm_create([d], L.Run(storage=1)) as ctx:
+            L.lbm_step(ctx, 150)            # graph chunks + single launches
+            res.append((L.lbm_get_populations(ctx), L.lbm_entropy_stats(ctx)))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]
+
+
+def test_graph_and_eager_paths_agree():
+    L = lbm()
+    f0 = wl.random_populations(9, 128, 64, seed=4, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    out = []
+    for flags in (0, L.LBM_RUN_NO_GRAPH):
+        d = dom2d(nx=128, ny=64, qe=1, limiter=3, f_init=f0)
+        with L.lbm_create([d], L.Run(storage=0, flags=flags, graph_chunk=8)) as ctx:
+            L.lbm_step(ctx, 37)
+            L.lbm_step(ctx, 16)
+            out.append((L.lbm_get_populations(ctx), L.lbm_entropy_stats(ctx)))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("n", [(1, 1), (2, 3), (5, 1), (257, 2)])
+def test_degenerate_small_periodic_grids(n):
+    f0 = wl.random_populations(9, n[0], n[1], seed=12, amp=0.05, spike_frac=0.2, spike_amp=0.4)
+    pr = Pair(dom2d(nx=n[0], ny=n[1], qe=1, limiter=3), f0, steps=2)
+    assert_masks_equal(pr)
+    fields_close(pr, rtol=1e-13)
+    assert_stats_close(pr)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5, 1.0])
+def test_special_betas_and_zero_threshold(beta):
+    f0 = wl.random_populations(9, 70, 30, seed=13, amp=0.05, spike_frac=0.05, spike_amp=0.4)
+    pr = Pair(dom2d(nx=70, ny=30, beta=beta, qe=0, limiter=3, delta_trim=0.0, delta_median=0.0), f0)
+    assert_masks_equal(pr)
+    fields_close(pr)
+    assert_stats_close(pr)
+
+
+def test_equilibrium_state_is_left_alone():
+    """All sites at f*: Delta S' = 0 everywhere, no site limited, median of zeros."""
+    L = lbm()
+    o = orc()
+    rho, u = wl.random_flow(90, 50, seed=8, umax=0.05)
+    f0 = o.init_equilibrium(o.make_params(lattice=2, nx=90, ny=50, qe=1), rho, u)
+    pr = Pair(dom2d(nx=90, ny=50, qe=1, limiter=3, delta_trim=0.0, delta_median=0.0), f0)
+    assert_masks_equal(pr)
+    fields_close(pr)
+
+
+def test_batched_cavities_match_single_domain_oracle_runs():
+    """Several cavities of different sizes and Re in one launch per step."""
+    L = lbm()
+    o = orc()
+    sizes = [(64, 2000.0), (100, 5000.0), (37, 3000.0), (128, 7500.0)]
+    doms, f0s = [], []
+    for k, (n, re) in enumerate(sizes):
+        f0 = wl.random_populations(9, n, n, seed=100 + k, rho0=1.0, amp=0.02, spike_frac=0.02, spike_amp=0.3)
+        f0s.append(f0)
+        doms.append(L.Domain(lattice=D2Q9, nx=n, ny=n, beta=wl.beta_from_nu(0.1 * n / re), qe=1, limiter=2, bc=1,
+                             rho0=1.0, lid_ux=0.1, delta_median=1e-5, f_init=f0,
+                             probe=(round((n - 1) / 16), round(13 * (n - 1) / 16))))
+    steps = 40
+    with L.lbm_create(doms, L.Run(storage=0, flags=L.LBM_RUN_RECORD)) as ctx:
+        L.lbm_step(ctx, steps)
+        res = [(L.lbm_get_populations(ctx, k), L.lbm_limiter_mask(ctx, k)[0], L.lbm_entropy_stats(ctx, k),
+                L.lbm_probe_trace(ctx, k)) for k in range(len(doms))]
+    for k, d in enumerate(doms):
+        say(f"[batch domain {k}] n={d.nx}")
+        p = o.make_params(lattice=2, nx=d.nx, ny=d.ny, beta=d.beta, qe=1, limiter=2, bc=1, rho0=1.0, lid_ux=0.1,
+                          delta_median=1e-5)
+        f = f0s[k].copy()
+        probe = []
+        for s in range(steps):
+            r, ux, uy = o.moments(2, f)
+            probe.append((ux[d.probe[1], d.probe[0]], uy[d.probe[1], d.probe[0]]))
+            st, mo, _ = o.step(p, f, 1, record=True)
+        fg, mg, sg, tr = res[k]
+        assert np.abs(fg - f).max() <= 1e-11 * np.abs(f).max()
+        assert np.array_equal(mg, mo)
+        assert sg["n_filtered"] == st.n_filtered and sg["sum_dS_post"] == pytest.approx(st.sum_dS_post, rel=1e-10)
+        assert tr.shape == (steps, 2)
+        assert np.allclose(tr, np.array(probe, dtype=np.float32), rtol=1e-5, atol=1e-7)
+
+
+def test_unstable_state_is_reported():
+    """A node with zero density makes u non-finite; the stats point reports it."""
+    L = lbm()
+    f0 = wl.random_populations(9, 64, 32, seed=1)
+    f0[:, 10, 10] = 0.0
+    d = dom2d(nx=64, ny=32, qe=0, f_init=f0)
+    with L.lbm_create([d], L.Run(storage=0)) as ctx:
+        L.lbm_step(ctx, 2)
+        s = L.lbm_entropy_stats(ctx, allow_unstable=True)
+        assert s.get("unstable") and s["n_nonfinite"] > 0
+        with pytest.raises(L.LbmError) as e:
+            L.lbm_entropy_stats(ctx)
+        assert e.value.code == L.LBM_EUNSTABLE
+    with L.lbm_create([dom2d(nx=64, ny=32, qe=0, f_init=f0)], L.Run(storage=0, stats_every=1)) as ctx:
+        with pytest.raises(L.LbmError) as e:
+            L.lbm_step(ctx, 5)
+        assert e.value.code == L.LBM_EUNSTABLE
