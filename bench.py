@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity batch")
+    ap.add_argument("--tile", default="", help="fixed tile 'TX,TH' instead of autotuning (profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of 1 GiB (known bytes) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -124,7 +127,11 @@ def main():
     n = args.n
     dom = c2_domain(L, wl, n)
     print(f"[bench] creating {n}x{n} FP32 context", file=sys.stderr, flush=True)
-    ctx = L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64))
+    run = L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)
+    if args.tile:
+        tx, th = (int(v) for v in args.tile.split(","))
+        run.tile_x, run.tile_y, run.tile_h = tx, 256 // tx, th
+    ctx = L.lbm_create([dom], run)
     tile = L.lbm_tile_config(ctx)
     print(f"[bench] tile {tile}; warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
     ms = time_steps(torch, L, ctx, stream, args.steps, args.warmup)
@@ -164,12 +171,26 @@ def main():
                   "max_dS": stats["max_dS"], "n_nonfinite": stats["n_nonfinite"]},
     }
     ctx.close()
+    if args.calibrate_copy:
+        out["copy_calibration"] = copy_calibration(torch, stream)
     if args.variants:
         out["variants"] = variants(torch, L, wl, stream, args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(torch, stream, nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of `nbytes` (read nbytes, write nbytes):
+    its FETCH_SIZE / WRITE_SIZE counters give the scale of those counters."""
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}
 
 
 def variants(torch, L, wl, stream, args):

@@ -26,6 +26,9 @@ COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b+c only inside one expression: every inlined copy of the site
+    # arithmetic (halo pass, main loop) then rounds identically
+    "-ffp-contract=on",
     "-I", INCLUDE, "-I", CSRC,
     "-Wall", "-Wno-unused-function", "-fvisibility=hidden",
 ]

@@ -86,10 +86,11 @@ hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u
 // inverts that map: o_i(x) = f_i(x + v_i), or f_opp(i)(x) when x + v_i is off
 // the grid.
 template <int LAT, class T>
-__global__ void k_scatter(const double* __restrict__ f, T* __restrict__ buf, long long plane, int nx, int ny,
+__global__ void k_scatter(const double* __restrict__ f, T* buf_, long long plane, int nx, int ny,
                           int periodic, double shift)
 {
     using L = Lat<LAT>;
+    const gptr<T> buf = to_global<T>(static_cast<void*>(buf_));
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = nx * ny;
     if (s >= n) return;
@@ -113,10 +114,11 @@ __global__ void k_scatter(const double* __restrict__ f, T* __restrict__ buf, lon
 
 // Gather: f_i(x) from the buffer as FP64; optionally rho and u (eq. macro_dis)
 template <int LAT, class T>
-__global__ void k_gather(const T* __restrict__ buf, long long plane, double* __restrict__ f, int nx, int ny,
+__global__ void k_gather(const T* buf_, long long plane, double* __restrict__ f, int nx, int ny,
                          int periodic, double shift, int want_f, double* __restrict__ rho, double* __restrict__ u)
 {
     using L = Lat<LAT>;
+    const gptr<const T> buf = to_global<T>(static_cast<const void*>(buf_));
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = nx * ny;
     if (s >= n) return;
@@ -181,8 +183,8 @@ hipError_t launch_scatter(int storage, int lattice, int bc, const double* f, voi
     switch (storage) {
     case kF64: return scatter_t<double>(lattice, periodic, f, buf, plane, nx, ny, shift, s);
     case kF32: return scatter_t<float>(lattice, periodic, f, buf, plane, nx, ny, shift, s);
-    case kF16: return scatter_t<__half>(lattice, periodic, f, buf, plane, nx, ny, shift, s);
-    case kBF16: return scatter_t<__hip_bfloat16>(lattice, periodic, f, buf, plane, nx, ny, shift, s);
+    case kF16: return scatter_t<_Float16>(lattice, periodic, f, buf, plane, nx, ny, shift, s);
+    case kBF16: return scatter_t<__bf16>(lattice, periodic, f, buf, plane, nx, ny, shift, s);
     }
     return hipErrorInvalidValue;
 }
@@ -194,8 +196,8 @@ hipError_t launch_gather(int storage, int lattice, int bc, const void* buf, long
     switch (storage) {
     case kF64: return gather_t<double>(lattice, periodic, buf, plane, f, nx, ny, shift, want_f, rho, u, s);
     case kF32: return gather_t<float>(lattice, periodic, buf, plane, f, nx, ny, shift, want_f, rho, u, s);
-    case kF16: return gather_t<__half>(lattice, periodic, buf, plane, f, nx, ny, shift, want_f, rho, u, s);
-    case kBF16: return gather_t<__hip_bfloat16>(lattice, periodic, buf, plane, f, nx, ny, shift, want_f, rho, u, s);
+    case kF16: return gather_t<_Float16>(lattice, periodic, buf, plane, f, nx, ny, shift, want_f, rho, u, s);
+    case kBF16: return gather_t<__bf16>(lattice, periodic, buf, plane, f, nx, ny, shift, want_f, rho, u, s);
     }
     return hipErrorInvalidValue;
 }

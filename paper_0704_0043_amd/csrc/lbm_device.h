@@ -9,8 +9,6 @@
 // quasiequilibria of Sec. 4.1.
 #pragma once
 
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "lbm_common.h"
@@ -58,32 +56,46 @@ struct Lat<kD1Q3> {
 };
 
 // ---- storage ---------------------------------------------------------------
+// Pointers into the population buffers are read from the domain table, so
+// the compiler cannot infer their address space; they are cast to global
+// (address space 1) so that loads and stores use global_* instructions
+// (flat ones would also count against the LDS wait counter).
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <class T>
+using gptr = LBM_GLOBAL T*;
+template <class T>
+__device__ inline gptr<T> to_global(void* p) { return (gptr<T>)p; }
+template <class T>
+__device__ inline gptr<const T> to_global(const void* p) { return (gptr<const T>)p; }
+
 template <class T>
 struct Store;
 
 template <>
 struct Store<double> {
     using A = double;
-    __device__ static A ld(const double* p) { return *p; }
-    __device__ static void st(double* p, A v) { *p = v; }
+    __device__ static A ld(gptr<const double> p) { return *p; }
+    __device__ static void st(gptr<double> p, A v) { *p = v; }
 };
 template <>
 struct Store<float> {
     using A = float;
-    __device__ static A ld(const float* p) { return *p; }
-    __device__ static void st(float* p, A v) { *p = v; }
+    __device__ static A ld(gptr<const float> p) { return *p; }
+    __device__ static void st(gptr<float> p, A v) { *p = v; }
+};
+// FP16 / BF16 storage uses the compiler's native _Float16 and __bf16 types
+// (round to nearest even on store).
+template <>
+struct Store<_Float16> {
+    using A = float;
+    __device__ static A ld(gptr<const _Float16> p) { return float(*p); }
+    __device__ static void st(gptr<_Float16> p, A v) { *p = (_Float16)v; }
 };
 template <>
-struct Store<__half> {
+struct Store<__bf16> {
     using A = float;
-    __device__ static A ld(const __half* p) { return __half2float(*p); }
-    __device__ static void st(__half* p, A v) { *p = __float2half_rn(v); }
-};
-template <>
-struct Store<__hip_bfloat16> {
-    using A = float;
-    __device__ static A ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
-    __device__ static void st(__hip_bfloat16* p, A v) { *p = __float2bfloat16(v); }
+    __device__ static A ld(gptr<const __bf16> p) { return float(*p); }
+    __device__ static void st(gptr<__bf16> p, A v) { *p = (__bf16)v; }
 };
 
 // ---- arithmetic helpers ------------------------------------------------------
@@ -355,12 +367,12 @@ struct Acc {
         if (!(isfinite(s.dr) && isfinite(s.jx) && isfinite(s.jy))) ++nonfin;
     }
     template <class A>
-    __device__ void fluid_site(const SiteScalars& s, A dpost)
+    __device__ void fluid_site(const SiteScalars& s, A site_dpost)
     {
         ++fluid;
         if (s.nonpos) ++nonpos;
         if (isfinite(s.dpre)) dpre += s.dpre;
-        double dp = double(dpost);
+        const double dp = double(site_dpost);
         if (isfinite(dp)) {
             dpost += dp;
             maxd = fmax(maxd, dp);

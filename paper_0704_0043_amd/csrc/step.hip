@@ -26,10 +26,10 @@ using StT = double;
 using StT = float;
 #define LBM_SUFFIX st1
 #elif LBM_ST == 2
-using StT = __half;
+using StT = _Float16;
 #define LBM_SUFFIX st2
 #else
-using StT = __hip_bfloat16;
+using StT = __bf16;
 #define LBM_SUFFIX st3
 #endif
 #define LBM_CAT2(a, b) a##_##b
@@ -41,7 +41,7 @@ namespace lbm {
 // one step earlier.  Off a non-periodic edge the value is the node's own
 // opposite population (reflection), which makes free flight a permutation.
 template <int LAT, int BC, class T>
-__device__ inline void gather(const T* __restrict__ src, long long plane, int nx, int ny, int x, int y,
+__device__ inline void gather(gptr<const T> src, long long plane, int nx, int ny, int x, int y,
                               typename Store<T>::A (&g)[Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(kThreads) k_step2d(StepArgs a)
     const int ncols = min(TX, nx - x0);
     const int hrows = y1 - y0 + 2;
     const long long plane = D.plane;
-    const T* __restrict__ src = static_cast<const T*>(D.buf[a.parity]);
-    T* __restrict__ dst = static_cast<T*>(D.buf[1 - a.parity]);
+    const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
+    const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
     const A shift = A(D.shift), c = A(D.c);
     const bool record = a.flags & kFlagRecord;
     const bool want_ent = a.flags & kFlagEntropy;
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kThreads) k_step2d(StepArgs a)
                         if (isfinite(e)) acc.ent += e;
                     }
                     if (x == D.probe_x && yy == D.probe_y) {
-                        float* p = D.probe + 2 * (step % D.probe_cap);
+                        const gptr<float> p = to_global<float>(D.probe) + 2 * (step % D.probe_cap);
                         p[0] = sc.ux;
                         p[1] = sc.uy;
                     }
@@ -296,8 +296,8 @@ __global__ void __launch_bounds__(kThreads) k_step2d(StepArgs a)
                     mask = kMaskNotFluid;
                 }
                 if (record) {
-                    D.mask[obase] = (unsigned char)mask;
-                    D.dS[obase] = double(dsrec);
+                    to_global<unsigned char>(D.mask)[obase] = (unsigned char)mask;
+                    to_global<double>(D.dS)[obase] = double(dsrec);
                 }
             }
         }
@@ -332,8 +332,8 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
     const int tid = threadIdx.x;
     const int nx = D.nx;
     const long long plane = D.plane;
-    const T* __restrict__ src = static_cast<const T*>(D.buf[a.parity]);
-    T* __restrict__ dst = static_cast<T*>(D.buf[1 - a.parity]);
+    const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
+    const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
     const A shift = A(D.shift), c = A(D.c);
     const long long step = a.counter[a.parity];
 
@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
                 if (isfinite(e)) acc.ent += e;
             }
             if (x == D.probe_x) {
-                float* p = D.probe + 2 * (step % D.probe_cap);
+                const gptr<float> p = to_global<float>(D.probe) + 2 * (step % D.probe_cap);
                 p[0] = sc.ux;
                 p[1] = 0.0f;
             }
@@ -380,8 +380,8 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
         if (phi < A(1) && isfinite(S.dpost)) acc.lim += double(S.dpost - delta_s_scaled<LAT, DS>(S, shift, c, phi));
         if (sc.nonpos) mask |= kMaskNonpos;
         if (a.flags & kFlagRecord) {
-            D.mask[x] = (unsigned char)mask;
-            D.dS[x] = double(S.dpost);
+            to_global<unsigned char>(D.mask)[x] = (unsigned char)mask;
+            to_global<double>(D.dS)[x] = double(S.dpost);
         }
     }
     store_partial(acc, a.partials + ((long long)a.parity * a.ntiles + xcd_spatial(blockIdx.x, a.ntiles)) * kNStat,

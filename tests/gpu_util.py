@@ -64,7 +64,35 @@ class Pair:
         self.fo = np.ascontiguousarray(f0, dtype=np.float64).copy()
         st, self.mo, self.dso = o.step(p, self.fo, steps, record=True)
         self.so = st.as_dict()
+        self.neq = neq_l1(dom, f0) if steps == 1 else None
         dom.f_init = None
+
+
+def neq_l1(dom, f0):
+    """sum_i |f'_i - f*_i| per node for one step from f0 (oracle equilibria):
+    the scale of the rounding error of Delta S(f') in any FP64 evaluation."""
+    o = orc()
+    f0 = np.asarray(f0, dtype=np.float64)
+    rho, ux, uy = o.moments(dom.lattice, f0)
+    c = 2 * dom.beta - 1
+    out = np.zeros(rho.shape)
+    for (y, x), r in np.ndenumerate(rho):
+        fs = o.equilibrium(dom.lattice, dom.qe, r, ux[y, x], uy[y, x])
+        out[y, x] = abs(c) * np.abs(fs - f0[:, y, x]).sum()
+    return out
+
+
+def stats_equal(a, b):
+    """dict equality with NaN == NaN (total_entropy is NaN when not computed)"""
+    if a.keys() != b.keys():
+        return False
+    for k in a:
+        x, y = a[k], b[k]
+        if isinstance(x, float) and isinstance(y, float) and np.isnan(x) and np.isnan(y):
+            continue
+        if x != y:
+            return False
+    return True
 
 
 def assert_masks_equal(pr):
@@ -76,13 +104,19 @@ def assert_masks_equal(pr):
 
 
 def assert_ds_close(pr, rtol):
+    """Delta S' within rtol, or within the rounding bound 32 eps sum|f' - f*|
+    where the nonequilibrium part is so small that one ulp of f* matters."""
     a, b = pr.ds, pr.dso
     fin = np.isfinite(b)
     assert np.array_equal(np.isfinite(a), fin)
     assert np.array_equal(np.isinf(a), np.isinf(b))
-    scale = np.maximum(np.abs(b[fin]), 1e-300)
-    err = np.abs(a[fin] - b[fin]) / scale
-    assert err.max(initial=0.0) <= rtol, f"dS rel err {err.max():.3e}"
+    tol = rtol * np.abs(b[fin])
+    if pr.neq is not None:
+        tol = tol + 32 * np.finfo(np.float64).eps * pr.neq[fin]
+    err = np.abs(a[fin] - b[fin])
+    bad = err > tol
+    assert not bad.any(), (f"{bad.sum()} dS mismatches, worst rel err "
+                           f"{(err / np.maximum(np.abs(b[fin]), 1e-300)).max():.3e}")
 
 
 def assert_stats_close(pr, rtol=1e-11, counts=True):
