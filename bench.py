@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity batch")
-    ap.add_argument("--tile", default="", help="fixed tile 'TX,TH' instead of autotuning (profiling runs)")
+    ap.add_argument("--tile-h", type=int, default=0, help="fixed rows per wave tile instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -128,9 +128,8 @@ def main():
     dom = c2_domain(L, wl, n)
     print(f"[bench] creating {n}x{n} FP32 context", file=sys.stderr, flush=True)
     run = L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)
-    if args.tile:
-        tx, th = (int(v) for v in args.tile.split(","))
-        run.tile_x, run.tile_y, run.tile_h = tx, 256 // tx, th
+    if args.tile_h:
+        run.tile_h = args.tile_h
     ctx = L.lbm_create([dom], run)
     tile = L.lbm_tile_config(ctx)
     print(f"[bench] tile {tile}; warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)

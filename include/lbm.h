@@ -125,9 +125,9 @@ typedef struct {
     int32_t device;             /* HIP device ordinal */
     int32_t stats_every;        /* >0: lbm_step synchronises every k steps and
                                    returns LBM_EUNSTABLE on non-finite moments */
-    int32_t tile_x, tile_y;     /* workgroup shape (tile_x * tile_y = 256);
-                                   0 = chosen by the autotuner */
-    int32_t tile_h;             /* rows per workgroup tile; 0 = autotuned */
+    int32_t tile_x, tile_y;     /* D2Q9 tiles are 256 columns (one workgroup,
+                                   one node per thread): pass 0 (or 256 and 1) */
+    int32_t tile_h;             /* rows per D2Q9 tile (1..64); 0 = autotuned */
     uint32_t flags;             /* LBM_RUN_* */
     int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
     int32_t graph_chunk;        /* steps per captured graph (even), 0 = 64 */
@@ -194,7 +194,7 @@ LBM_API int lbm_limiter_mask(lbm_ctx* ctx, int32_t domain, uint8_t* mask, double
 LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples,
                     int64_t* n_written);
 
-/* Tile shape in use (after autotuning). */
+/* Tile shape in use (after autotuning): columns, 1, rows (D1Q3: 254, 1, 1). */
 LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
 
 /* Release everything the context owns.  NULL is accepted. */

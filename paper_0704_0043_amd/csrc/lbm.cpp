@@ -24,6 +24,11 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t kAlign = 256;
+constexpr int kMinTileH = 4;              // smallest autotuned D2Q9 tile height
+constexpr int k1DWidth = kThreads - 2;    // output sites of one D1Q3 workgroup
+
+// D2Q9 tiles: kThreads consecutive columns
+int strips_of(int nx) { return (nx + kThreads - 1) / kThreads; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -43,7 +48,8 @@ struct DomainHost {
     int q = 0;
     long long plane = 0;
     size_t n = 0;
-    size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0;
+    size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0, off_dsbuf = 0;
+    bool dsbuf = false;
     double shift = 0;
     int tile_first = 0, tile_count = 0;
 };
@@ -67,12 +73,13 @@ struct lbm_ctx {
     Layout lay;
     char* ws = nullptr;
     bool own_ws = false;
-    int tx = 256, ty = 1, th = 64;
+    int th = 16;            // rows per D2Q9 tile
     int ntiles = 0;
+    bool median_pass = false;   // D2Q9 with the median filter in some domain
     long long steps_done = 0, finalized_for = -1;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
-    std::vector<double> tune_log;   // (tx, th, us) triples
+    std::vector<double> tune_log;   // (rows per tile, us per step) pairs
     std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
     std::vector<DomainDev> dom_host;
 
@@ -106,11 +113,10 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
     if (!doms || nd < 1 || !run) return fail(nullptr, LBM_EINVAL, "domains/run must be non-NULL, n_domains >= 1");
     if (run->struct_size < sizeof(lbm_run_desc)) return fail(nullptr, LBM_EINVAL, "lbm_run_desc.struct_size too small");
     if (run->storage < LBM_F64 || run->storage > LBM_BF16_SHIFT) return fail(nullptr, LBM_EINVAL, "bad storage");
-    if (run->tile_x != 0 && run->tile_x != 64 && run->tile_x != 128 && run->tile_x != 256)
-        return fail(nullptr, LBM_EINVAL, "tile_x must be 0, 64, 128 or 256");
-    if (run->tile_x != 0 && run->tile_y != 0 && run->tile_x * run->tile_y != kThreads)
-        return fail(nullptr, LBM_EINVAL, "tile_x * tile_y must be 256");
-    if (run->tile_h < 0 || run->tile_h > kMaxTileH) return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 510]");
+    if (run->tile_x != 0 && run->tile_x != kThreads)
+        return fail(nullptr, LBM_EINVAL, "tile_x must be 0 or 256 (columns of one tile)");
+    if (run->tile_y != 0 && run->tile_y != 1) return fail(nullptr, LBM_EINVAL, "tile_y must be 0 or 1");
+    if (run->tile_h < 0 || run->tile_h > kMaxTileH) return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 64]");
     if (run->graph_chunk < 0 || (run->graph_chunk % 2) != 0) return fail(nullptr, LBM_EINVAL, "graph_chunk must be even");
     if (run->probe_capacity < 0) return fail(nullptr, LBM_EINVAL, "probe_capacity < 0");
     const lbm_domain_desc& d0 = doms[0];
@@ -210,9 +216,14 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         }
         h.off_stats = off;
         off = align_up(off + (kNStat + 1) * sizeof(double), kAlign);
-        const int tiles = h.d.lattice == LBM_D2Q9
-                              ? ((h.d.nx + 63) / 64) * ((h.d.ny + 15) / 16)
-                              : (h.d.nx + kThreads - 3) / (kThreads - 2);
+        h.dsbuf = h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN);
+        if (h.dsbuf) {
+            h.off_dsbuf = off;
+            off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
+        }
+        const int min_h = run->tile_h > 0 ? std::min(run->tile_h, kMinTileH) : kMinTileH;
+        const int tiles = h.d.lattice == LBM_D2Q9 ? strips_of(h.d.nx) * ((h.d.ny + min_h - 1) / min_h)
+                                                  : (h.d.nx + k1DWidth - 1) / k1DWidth;
         L.max_tiles += tiles;
         L.max_n = std::max(L.max_n, h.n);
     }
@@ -221,7 +232,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     L.off_tiles = off;
     off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
     L.off_partials = off;
-    off = align_up(off + size_t(2) * L.max_tiles * kNStat * sizeof(double), kAlign);
+    off = align_up(off + size_t(4) * L.max_tiles * kNStat * sizeof(double), kAlign);
     L.off_counter = off;
     off = align_up(off + 2 * sizeof(long long), kAlign);
     L.off_stage = off;
@@ -229,31 +240,29 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     L.total = off;
 }
 
-// Spatial tile order: domain, row chunk, column strip.  The table is indexed
-// by block id; xcd_spatial() gives each block its spatial tile, so every XCD
-// runs one contiguous stretch of the grid (strips sharing halo columns and
-// chunks sharing halo rows hit the same L2) while per-domain partial ranges
-// stay contiguous in spatial order.
-std::vector<Tile> build_tiles(lbm_ctx* ctx, int tx, int th)
+// Tiles in spatial order: domain, row block, column block.  A D2Q9 tile is
+// kThreads consecutive columns by `th` rows (one thread per column walking
+// the rows).  The kernels map workgroups to runs of this order XCD by XCD
+// (xcd_spatial), so vertically adjacent tiles, which share halo rows, run
+// on the same L2, and per-domain partial ranges stay contiguous.
+std::vector<Tile> build_tiles(lbm_ctx* ctx, int th)
 {
     std::vector<Tile> spatial;
     for (size_t k = 0; k < ctx->dom.size(); ++k) {
         DomainHost& h = ctx->dom[k];
         h.tile_first = int(spatial.size());
+        const int nx = h.d.nx, ny = h.d.ny;
         if (ctx->lattice == LBM_D2Q9) {
-            const int h_rows = std::min(th, h.d.ny);
-            for (int y0 = 0; y0 < h.d.ny; y0 += h_rows)
-                for (int x0 = 0; x0 < h.d.nx; x0 += tx)
-                    spatial.push_back(Tile{int(k), x0, y0, std::min(y0 + h_rows, h.d.ny)});
+            for (int y0 = 0; y0 < ny; y0 += th)
+                for (int x0 = 0; x0 < nx; x0 += kThreads)
+                    spatial.push_back(Tile{int(k), x0, std::min(x0 + kThreads, nx), y0, std::min(y0 + th, ny), 0, 0, 0});
         } else {
-            for (int x0 = 0; x0 < h.d.nx; x0 += kThreads - 2) spatial.push_back(Tile{int(k), x0, 0, 1});
+            for (int x0 = 0; x0 < nx; x0 += k1DWidth)
+                spatial.push_back(Tile{int(k), x0, std::min(x0 + k1DWidth, nx), 0, 1, 0, 0, 0});
         }
         h.tile_count = int(spatial.size()) - h.tile_first;
     }
-    const int T = int(spatial.size());
-    std::vector<Tile> by_block(T);
-    for (int b = 0; b < T; ++b) by_block[b] = spatial[xcd_spatial(b, T)];
-    return by_block;
+    return spatial;
 }
 
 int upload_domains(lbm_ctx* ctx)
@@ -286,19 +295,18 @@ int upload_domains(lbm_ctx* ctx)
         d.tile_first = h.tile_first;
         d.tile_count = h.tile_count;
         d.stats = reinterpret_cast<double*>(ctx->ws + h.off_stats);
+        d.dsbuf = h.dsbuf ? ctx->ws + h.off_dsbuf : nullptr;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_dom(), dd.data(), dd.size() * sizeof(DomainDev), hipMemcpyHostToDevice,
                                 ctx->stream));
     return LBM_OK;
 }
 
-int set_tiles(lbm_ctx* ctx, int tx, int th)
+int set_tiles(lbm_ctx* ctx, int th)
 {
-    ctx->tiles_host = build_tiles(ctx, tx, th);
+    ctx->tiles_host = build_tiles(ctx, th);
     if (int(ctx->tiles_host.size()) > ctx->lay.max_tiles) return fail(ctx, LBM_EINVAL, "tile table overflow");
     ctx->ntiles = int(ctx->tiles_host.size());
-    ctx->tx = tx;
-    ctx->ty = kThreads / tx;
     ctx->th = th;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tiles(), ctx->tiles_host.data(), ctx->tiles_host.size() * sizeof(Tile),
                                 hipMemcpyHostToDevice, ctx->stream));
@@ -315,11 +323,11 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.tiles = ctx->d_tiles();
     a.ntiles = ctx->ntiles;
     a.ndomains = int(ctx->dom.size());
+    a.median_pass = ctx->median_pass ? 1 : 0;
     a.parity = parity;
     a.flags = ctx->flags & (LBM_RUN_RECORD | LBM_RUN_ENTROPY);
     a.partials = ctx->d_partials();
     a.counter = ctx->d_counter();
-    a.tile_w = ctx->lattice == LBM_D2Q9 ? ctx->tx : kThreads - 2;
     return a;
 }
 
@@ -328,7 +336,7 @@ int launch_one(lbm_ctx* ctx, int parity)
     const StepArgs a = step_args(ctx, parity);
     hipError_t e;
     if (ctx->lattice == LBM_D2Q9)
-        e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->tx, ctx->ty, ctx->th, ctx->stream);
+        e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->median_pass, ctx->stream);
     else
         e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -355,57 +363,47 @@ void drop_graphs(lbm_ctx* ctx)
         }
 }
 
-// Time candidate tile shapes on the live state (reads buffer 0, writes
+// Time candidate tile heights on the live state (reads buffer 0, writes
 // buffer 1, which the first real step overwrites anyway).
-int autotune(lbm_ctx* ctx, int fixed_tx, int fixed_th)
+int autotune(lbm_ctx* ctx, int fixed_th)
 {
-    std::vector<int> txs = fixed_tx ? std::vector<int>{fixed_tx} : std::vector<int>{256, 128, 64};
     int max_ny = 0;
     for (const auto& h : ctx->dom) max_ny = std::max(max_ny, h.d.ny);
+    if (fixed_th) return set_tiles(ctx, fixed_th);
     std::vector<int> ths;
-    if (fixed_th) {
-        ths.push_back(fixed_th);
-    } else {
-        for (int th : {16, 32, 64, 128, 256, 510})
-            if (th <= std::max(16, max_ny)) ths.push_back(th);
-        if (max_ny < 510 && std::find(ths.begin(), ths.end(), max_ny) == ths.end() && max_ny >= 16)
-            ths.push_back(max_ny);
-    }
-    if (txs.size() * ths.size() == 1 || (ctx->flags & LBM_RUN_NO_TUNE)) {
-        return set_tiles(ctx, txs[0], ths.size() == 1 ? ths[0] : std::min(64, std::max(16, max_ny)));
-    }
+    for (int th : {4, 8, 16, 32, 64})
+        if (th <= std::max(kMinTileH, max_ny)) ths.push_back(th);
+    if (ths.size() == 1 || (ctx->flags & LBM_RUN_NO_TUNE))
+        return set_tiles(ctx, std::min(16, std::max(kMinTileH, max_ny)));
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     double best = 1e300;
-    int btx = txs[0], bth = ths[0];
-    for (int tx : txs)
-        for (int th : ths) {
-            int rc = set_tiles(ctx, tx, th);
-            if (rc) return rc;
-            for (int w = 0; w < 2; ++w)
-                if ((rc = launch_one(ctx, 0))) return rc;
-            const int reps = 5;
-            HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
-            for (int r = 0; r < reps; ++r)
-                if ((rc = launch_one(ctx, 0))) return rc;
-            HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
-            HIP_TRY(ctx, hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
-            const double us = 1000.0 * ms / reps;
-            ctx->tune_log.push_back(tx);
-            ctx->tune_log.push_back(th);
-            ctx->tune_log.push_back(us);
-            if (us < best) {
-                best = us;
-                btx = tx;
-                bth = th;
-            }
+    int bth = ths[0];
+    for (int th : ths) {
+        int rc = set_tiles(ctx, th);
+        if (rc) return rc;
+        for (int w = 0; w < 2; ++w)
+            if ((rc = launch_one(ctx, 0))) return rc;
+        const int reps = 5;
+        HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+        for (int r = 0; r < reps; ++r)
+            if ((rc = launch_one(ctx, 0))) return rc;
+        HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+        HIP_TRY(ctx, hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1000.0 * ms / reps;
+        ctx->tune_log.push_back(th);
+        ctx->tune_log.push_back(us);
+        if (us < best) {
+            best = us;
+            bth = th;
         }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return set_tiles(ctx, btx, bth);
+    return set_tiles(ctx, bth);
 }
 
 int capture(lbm_ctx* ctx, int parity)
@@ -548,6 +546,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     ctx->probe_cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;
     ctx->graph_chunk = run->graph_chunk > 0 ? run->graph_chunk : 64;
     plan(ctx->dom, domains, n_domains, run, ctx->lay);
+    for (const auto& h : ctx->dom) ctx->median_pass = ctx->median_pass || h.dsbuf;
 
     auto bail = [&](int code) {
         release(ctx);
@@ -606,7 +605,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("init: ") + hipGetErrorString(e)));
     }
-    rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run->tile_x, run->tile_h) : set_tiles(ctx, kThreads - 2, 1);
+    rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run->tile_h) : set_tiles(ctx, 1);
     if (rc) {
         g_err = ctx->err;
         return bail(rc);
@@ -767,9 +766,10 @@ int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples
 int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h)
 {
     if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
-    if (tile_x) *tile_x = ctx->tx;
-    if (tile_y) *tile_y = ctx->ty;
-    if (tile_h) *tile_h = ctx->th;
+    const bool d2 = ctx->lattice == LBM_D2Q9;
+    if (tile_x) *tile_x = d2 ? kThreads : k1DWidth;
+    if (tile_y) *tile_y = 1;
+    if (tile_h) *tile_h = d2 ? ctx->th : 1;
     return LBM_OK;
 }
 

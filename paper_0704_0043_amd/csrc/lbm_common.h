@@ -16,8 +16,9 @@ enum { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8 };
 enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2 };
 
-constexpr int kThreads = 256;      // workgroup size of the step kernels
-constexpr int kMaxTileH = 510;     // rows per 2-D tile (halo buffer bound)
+constexpr int kThreads = 256;      // workgroup size of the step kernels (= D2Q9 tile width)
+constexpr int kWave = 64;          // wavefront size (CDNA)
+constexpr int kMaxTileH = 64;      // rows per D2Q9 tile
 constexpr int kNStat = 13;         // FP64 values per tile partial
 
 // partial / stats slot layout (FP64 each)
@@ -44,6 +45,7 @@ struct DomainDev {
     double* dS;             // [ny*nx] when recording
     int tile_first, tile_count;   // this domain's range in the tile table
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
+    void* dsbuf;            // [ny*nx] Delta S' of the last collision (arithmetic type), median only
 };
 
 constexpr int kXcds = 8;   // MI355X: 8 accelerator dies, each with its own L2
@@ -59,26 +61,25 @@ __host__ __device__ inline int xcd_spatial(int b, int T)
     return x * q + (x < r ? x : r) + j;
 }
 
-// one work item: a strip of columns [x0, x0 + width) and rows [y0, y1)
+// one work item (one workgroup): columns [x0, x1), rows [y0, y1) of one domain
 struct Tile {
-    int domain, x0, y0, y1;
+    int domain, x0, x1, y0, y1, pad0, pad1, pad2;
 };
 
 struct StepArgs {
     const DomainDev* dom;
-    const Tile* tiles;      // indexed by blockIdx.x (XCD-aware order)
-    int ntiles;             // grid has ntiles + 1 blocks; the last one reduces
+    const Tile* tiles;      // spatial order (domain, row chunk, column strip)
+    int ntiles;             // the collision grid has ntiles + 1 blocks; block 0 reduces
     int ndomains;
     int parity;             // read buf[parity], write buf[1 - parity]
     unsigned flags;
-    double* partials;       // [2][ntiles][kNStat], indexed by spatial tile
+    double* partials;       // [2 parities][2 kernels][ntiles][kNStat], by spatial tile
+    int median_pass;        // 1 if the median kernel runs after the collision kernel
     long long* counter;     // [2] step index by parity
-    int tile_w;             // strip width in columns (threads along x)
 };
 
 // Launchers (one per storage type / lattice), defined in the .hip files.
-hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int tx, int ty,
-                         int tile_h, hipStream_t s);
+hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, bool median, hipStream_t s);
 hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);
 hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u, double* f, int nx, int ny,

@@ -68,6 +68,19 @@ __device__ inline gptr<T> to_global(void* p) { return (gptr<T>)p; }
 template <class T>
 __device__ inline gptr<const T> to_global(const void* p) { return (gptr<const T>)p; }
 
+// uniform base (SGPRs) + 32-bit byte offset (VGPR): lets the compiler use
+// the global_load/store "saddr + voffset" form instead of 64-bit lane addresses
+template <class T>
+__device__ __forceinline__ gptr<const T> at_bytes(gptr<const T> base, unsigned off)
+{
+    return (gptr<const T>)((gptr<const char>)base + off);
+}
+template <class T>
+__device__ __forceinline__ gptr<T> at_bytes(gptr<T> base, unsigned off)
+{
+    return (gptr<T>)((gptr<char>)base + off);
+}
+
 template <class T>
 struct Store;
 
@@ -174,7 +187,7 @@ __device__ inline void axis_excess(A u, A& x0, A& xm, A& xp)
 }
 
 template <int LAT, int QE, class A>
-__device__ inline void eq_excess(A ux, A uy, A (&E)[Lat<LAT>::Q])
+__device__ __forceinline__ void eq_excess(A ux, A uy, A (&E)[Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
     if constexpr (QE == kPoly) {
@@ -219,7 +232,7 @@ struct SiteScalars {
 };
 
 template <int LAT, int QE, int DS, class A>
-__device__ inline void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, SiteState<LAT, A>& o,
+__device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, SiteState<LAT, A>& o,
                                     SiteScalars& sc, bool want_pre)
 {
     using L = Lat<LAT>;
@@ -289,7 +302,7 @@ __device__ inline void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, Sit
 // Delta S of f* + s (f' - f*) = f* - s c d, used for the limiter's entropy
 // production (eq. LimEntLim).
 template <int LAT, int DS, class A>
-__device__ inline A delta_s_scaled(const SiteState<LAT, A>& o, A shift, A c, A s)
+__device__ __forceinline__ A delta_s_scaled(const SiteState<LAT, A>& o, A shift, A c, A s)
 {
     using L = Lat<LAT>;
     if constexpr (DS == kQuad) {
@@ -324,7 +337,7 @@ __device__ inline double entropy_site(const A (&g)[Lat<LAT>::Q], A shift)
 // phi for one fluid site (eq. LimGenF): trimming (eq. entrHom / Ehrenfests'
 // step) and the median filter (Sec. 3.5); both on -> the smaller phi.
 template <class A>
-__device__ inline A limiter_phi(A dpost, bool has_med, A med, const DomainDev& D, unsigned& mask)
+__device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const DomainDev& D, unsigned& mask)
 {
     A phi = A(1);
     if (D.limiter & kLimTrim) {
@@ -355,15 +368,20 @@ __device__ inline A limiter_phi(A dpost, bool has_med, A med, const DomainDev& D
 }
 
 // ---- statistics ----------------------------------------------------------------
-struct Acc {
-    double mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
+// Per-thread running sums over the (at most 64) nodes a thread visits, kept
+// in type S: FP64 in FP64 mode, FP32 in the reduced-storage modes (a
+// 64-term FP32 sum of FP32 site values loses nothing that matters); the
+// workgroup, tile, domain and global reductions are FP64.
+template <class S>
+struct AccT {
+    S mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
     int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0;
 
     __device__ void moments(const SiteScalars& s)
     {
-        mass += s.dr;
-        jx += s.jx;
-        jy += s.jy;
+        mass += S(s.dr);
+        jx += S(s.jx);
+        jy += S(s.jy);
         if (!(isfinite(s.dr) && isfinite(s.jx) && isfinite(s.jy))) ++nonfin;
     }
     template <class A>
@@ -371,22 +389,24 @@ struct Acc {
     {
         ++fluid;
         if (s.nonpos) ++nonpos;
-        if (isfinite(s.dpre)) dpre += s.dpre;
-        const double dp = double(site_dpost);
+        if (isfinite(s.dpre)) dpre += S(s.dpre);
+        const S dp = S(site_dpost);
         if (isfinite(dp)) {
             dpost += dp;
             maxd = fmax(maxd, dp);
         }
     }
 };
+using Acc = AccT<double>;
 
 // Deterministic workgroup reduction of the accumulators into one partial
 // (fixed butterfly inside each wave, then waves in order).
-__device__ inline void store_partial(const Acc& acc, double* out, double* lds /* [4 * kNStat] */)
+template <class S>
+__device__ inline void store_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */)
 {
-    double v[kNStat] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent,
-                        double(acc.trim), double(acc.filt), double(acc.nonpos), double(acc.nonfin),
-                        double(acc.fluid)};
+    double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
+                        double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
+                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -410,15 +430,15 @@ __device__ inline void store_partial(const Acc& acc, double* out, double* lds /*
     }
 }
 
-// Reduce the partials of the step that ran with `parity` into each domain's
-// stats slot (fixed order per domain).  Run by one workgroup.
 constexpr int kSmallDomainTiles = 32;
 
 __device__ inline void reduce_partials(const StepArgs& a, int parity, long long step, double* lds)
 {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthr = blockDim.x * blockDim.y;
-    const double* part = a.partials + (long long)parity * a.ntiles * kNStat;
+    // partials of the collision kernel, then (if it ran) of the median kernel
+    const double* part = a.partials + (long long)parity * 2 * a.ntiles * kNStat;
+    const int nsets = a.median_pass ? 2 : 1;
     // domains with few tiles: one thread each, tiles summed in order
     for (int d = tid; d < a.ndomains; d += nthr) {
         const DomainDev& D = a.dom[d];
@@ -426,11 +446,12 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
         double v[kNStat];
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) v[k] = 0;
-        for (int t = 0; t < D.tile_count; ++t) {
-            const double* p = part + (long long)(D.tile_first + t) * kNStat;
+        for (int set = 0; set < nsets; ++set)
+            for (int t = 0; t < D.tile_count; ++t) {
+                const double* p = part + ((long long)set * a.ntiles + D.tile_first + t) * kNStat;
 #pragma unroll
-            for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
-        }
+                for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
+            }
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) D.stats[k] = v[k];
         D.stats[kNStat] = double(step);
@@ -442,11 +463,12 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
         double v[kNStat];
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) v[k] = 0;
-        for (int t = tid; t < D.tile_count; t += nthr) {
-            const double* p = part + (long long)(D.tile_first + t) * kNStat;
+        for (int set = 0; set < nsets; ++set)
+            for (int t = tid; t < D.tile_count; t += nthr) {
+                const double* p = part + ((long long)set * a.ntiles + D.tile_first + t) * kNStat;
 #pragma unroll
-            for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
-        }
+                for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
+            }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll

@@ -1,19 +1,27 @@
 // Fused limited LBGK step kernels for gfx950.
 //
-// Compiled once per population storage type (LBM_ST = 0..3).  One launch is
-// one time step of every domain in the tile table: free flight (pull form,
-// read from buffer `parity`), moments, f*, over-relaxation, Delta S(f'),
-// trimming and/or the median filter, and the store of the limited
-// post-collision state into the other buffer.  The last workgroup of the grid
-// reduces the previous step's per-tile FP64 partials into the domain stats.
+// Compiled once per population storage type (LBM_ST = 0..3).  A time step of
+// every domain in the tile table is one launch of the collision kernel and,
+// when the median filter is on, one launch of the median kernel:
 //
-// Memory layout: SoA planes buf[i * plane + y * nx + x].  Each D2Q9 workgroup
-// owns a strip of TX columns and rows [y0, y1) and walks down it with TY rows
-// per iteration ("sliding window"): Delta S' of the current row block goes
-// into an LDS ring of four row blocks, so the 3x3 median of a row needs no
-// recomputation of its neighbours; the two halo columns of the strip are
-// computed once per tile before the walk.  Loads of the next row block are
-// issued before the current block is processed.
+//  collision: one thread per node, 256 consecutive columns x R rows per
+//    workgroup.  Free flight (pull form, read from buffer `parity`), moments,
+//    f*, over-relaxation, Delta S', the trimming factor (it depends on the
+//    node alone), and the store of the limited post-collision state into the
+//    other buffer.  With the median filter on, Delta S' also goes to a plane
+//    of its own.
+//  median: the 3x3 median of that plane decides the filter; the few nodes
+//    whose factor drops below the trimming factor are collided again (the
+//    same arithmetic, bit-identical) from the untouched source buffer and
+//    overwritten.
+//
+// Both kernels are plain streaming passes with one node per lane, aligned
+// stores and no barrier in the node loop, the access pattern that sustains
+// the highest HBM bandwidth on this part.  Block 0 of the collision grid
+// reduces the previous step's per-tile FP64 partials into the domain stats
+// while the other blocks run.
+#include <type_traits>
+
 #include "lbm_device.h"
 
 #ifndef LBM_ST
@@ -36,40 +44,6 @@ using StT = __bf16;
 #define LBM_CAT(a, b) LBM_CAT2(a, b)
 
 namespace lbm {
-
-// Pull free flight: the population i arriving at (x, y) left (x - vx, y - vy)
-// one step earlier.  Off a non-periodic edge the value is the node's own
-// opposite population (reflection), which makes free flight a permutation.
-template <int LAT, int BC, class T>
-__device__ inline void gather(gptr<const T> src, long long plane, int nx, int ny, int x, int y,
-                              typename Store<T>::A (&g)[Lat<LAT>::Q])
-{
-    using L = Lat<LAT>;
-    if constexpr (BC == kPeriodic) {
-        const int xm = x == 0 ? nx - 1 : x - 1;
-        const int xp = x == nx - 1 ? 0 : x + 1;
-        unsigned r0 = unsigned(y) * unsigned(nx), rm = r0, rp = r0;
-        if constexpr (LAT == kD2Q9) {
-            rm = unsigned(y == 0 ? ny - 1 : y - 1) * unsigned(nx);
-            rp = unsigned(y == ny - 1 ? 0 : y + 1) * unsigned(nx);
-        }
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const int xs = L::vx(i) > 0 ? xm : (L::vx(i) < 0 ? xp : x);
-            const unsigned rs = L::vy(i) > 0 ? rm : (L::vy(i) < 0 ? rp : r0);
-            g[i] = Store<T>::ld(src + i * plane + (rs + unsigned(xs)));
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const int xs = x - L::vx(i), ys = y - L::vy(i);
-            const bool in = xs >= 0 && xs < nx && ys >= 0 && ys < ny;
-            const long long off = in ? (i * plane + (unsigned(ys) * unsigned(nx) + unsigned(xs)))
-                                     : (L::opp(i) * plane + (unsigned(y) * unsigned(nx) + unsigned(x)));
-            g[i] = Store<T>::ld(src + off);
-        }
-    }
-}
 
 // node classes of the cavity (Sec. 4.4.1): walls x = 0, x = nx-1, y = 0
 // (corners included), lid y = ny-1, fluid elsewhere
@@ -95,239 +69,342 @@ __device__ inline void reduce_block(const StepArgs& a, double* red)
     if (threadIdx.x == 0 && threadIdx.y == 0) a.counter[1 - a.parity] = step + 1;
 }
 
-template <class T, int QE, int DS, int BC>
-__global__ void __launch_bounds__(kThreads) k_step2d(StepArgs a)
+// spatial tile of a workgroup: blocks are spread over the XCDs so that each
+// XCD runs one contiguous stretch of tiles (rows sharing halo lines hit the
+// same L2).  `first` is the block id of tile 0.
+__device__ inline int tile_of_block(const StepArgs& a, int first)
+{
+    return xcd_spatial(int(blockIdx.x) - first, a.ntiles);
+}
+
+__device__ inline double* partial_slot(const StepArgs& a, int kernel, int tile)
+{
+    return a.partials + (((long long)a.parity * 2 + kernel) * a.ntiles + tile) * kNStat;
+}
+
+// trimming factor of one node (it depends on the node alone, Sec. 3.2/3.4)
+template <class A>
+__device__ __forceinline__ A trim_phi(const DomainDev& D, A dpost, unsigned& mask)
+{
+    A phi = A(1);
+    if ((D.limiter & kLimTrim) && dpost > A(D.delta_trim)) {
+        mask |= kMaskTrim;
+        phi = D.trim_mode ? A(0) : sqrt_(A(D.delta_trim) * rcp(dpost));
+    }
+    return phi;
+}
+
+// Columns of one thread: pull sources of movers with vx = +1, 0, -1 as byte
+// offsets (periodic wrap), and the thread's own column.
+template <class T, int BC>
+struct Cols {
+    unsigned m, c, p, own;
+    int x;
+    bool ok;
+    __device__ Cols(int x_, int nx, bool in) : x(x_), ok(in)
+    {
+        constexpr unsigned es = sizeof(T);
+        if constexpr (BC == kPeriodic) {
+            m = es * unsigned(x == 0 ? nx - 1 : x - 1);
+            p = es * unsigned(x == nx - 1 ? 0 : x + 1);
+        } else {
+            m = es * unsigned(x - 1);
+            p = es * unsigned(x + 1);
+        }
+        c = es * unsigned(x);
+        own = c;
+    }
+};
+
+// pull free flight of node (x, y): population i arriving there left
+// (x - vx, y - vy); off a non-periodic edge it is the node's own opposite
+// population (reflection: free flight stays a permutation)
+template <int BC, class T>
+__device__ __forceinline__ void gather2d(gptr<const T> src, long long plane, int nx, int ny, const Cols<T, BC>& cl,
+                                         int y, typename Store<T>::A (&g)[9])
+{
+    using L = Lat<kD2Q9>;
+    if constexpr (BC == kPeriodic) {
+        const long long r0 = (long long)y * nx;
+        const long long rm = (long long)(y == 0 ? ny - 1 : y - 1) * nx;
+        const long long rp = (long long)(y == ny - 1 ? 0 : y + 1) * nx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const long long rs = L::vy(i) > 0 ? rm : (L::vy(i) < 0 ? rp : r0);
+            const unsigned cs = L::vx(i) > 0 ? cl.m : (L::vx(i) < 0 ? cl.p : cl.c);
+            g[i] = Store<T>::ld(at_bytes(src + (i * plane + rs), cs));
+        }
+    } else {
+        const int x = cl.x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int xs = x - L::vx(i), ys = y - L::vy(i);
+            const bool in = xs >= 0 && xs < nx && ys >= 0 && ys < ny;
+            const long long off = in ? (i * plane + (long long)ys * nx + xs)
+                                     : (L::opp(i) * plane + (long long)y * nx + x);
+            g[i] = Store<T>::ld(src + off);
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void store_limited(gptr<T> dst, long long plane, long long row, unsigned own,
+                                              const SiteState<kD2Q9, typename Store<T>::A>& S,
+                                              typename Store<T>::A phi, typename Store<T>::A c)
 {
     using A = typename Store<T>::A;
-    constexpr int LAT = kD2Q9;
-    using L = Lat<LAT>;
-    constexpr int Q = L::Q;
-    __shared__ A ring[4 * (kThreads + 8)];
-    __shared__ A halo[2 * (kMaxTileH + 2)];
-    __shared__ double red[4 * kNStat];
+    const A k = phi * c;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Store<T>::st(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
+}
 
-    if (int(blockIdx.x) == a.ntiles) {
+template <class T, int QE, int DS, int BC>
+__global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
+{
+    using A = typename Store<T>::A;
+    using L = Lat<kD2Q9>;
+    constexpr int Q = 9;
+    __shared__ double red[4 * kNStat];
+    if (blockIdx.x == 0) {
         reduce_block(a, red);
         return;
     }
-    const Tile t = a.tiles[blockIdx.x];
+    const int tidx = tile_of_block(a, 1);
+    const Tile t = a.tiles[tidx];
     const DomainDev& D = a.dom[t.domain];
-    const int TX = blockDim.x, TY = blockDim.y;
-    const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * TX + lx;
     const int nx = D.nx, ny = D.ny;
-    const int x0 = t.x0, y0 = t.y0, y1 = t.y1;
-    const int ncols = min(TX, nx - x0);
-    const int hrows = y1 - y0 + 2;
     const long long plane = D.plane;
     const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
     const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
+    const gptr<A> dsb = to_global<A>(D.dsbuf);
     const A shift = A(D.shift), c = A(D.c);
     const bool record = a.flags & kFlagRecord;
     const bool want_ent = a.flags & kFlagEntropy;
+    const bool keep_ds = D.limiter & kLimMedian;
     const long long step = a.counter[a.parity];
-
-    // halo columns x0 - 1 and x0 + ncols for rows y0 - 1 .. y1: Delta S' only
-    for (int s = tid; s < 2 * hrows; s += kThreads) {
-        const int side = s >= hrows;
-        int hx = side ? x0 + ncols : x0 - 1;
-        int hy = y0 - 1 + (s - side * hrows);
-        A val = A(0);
-        bool fluid;
-        if constexpr (BC == kPeriodic) {
-            hx = wrapi(hx, nx);
-            hy = wrapi(hy, ny);
-            fluid = true;
-        } else {
-            fluid = hx >= 1 && hx <= nx - 2 && hy >= 1 && hy <= ny - 2;
-        }
-        if (fluid) {
+    const Cols<T, BC> cl(t.x0 + int(threadIdx.x), nx, t.x0 + int(threadIdx.x) < t.x1);
+    AccT<A> acc;
+    if (cl.ok) {
+        // loads of the next row are issued before the current row is processed
+        A gn[Q];
+        gather2d<BC>(src, plane, nx, ny, cl, t.y0, gn);
+        for (int y = t.y0; y < t.y1; ++y) {
             A g[Q];
-            gather<LAT, BC>(src, plane, nx, ny, hx, hy, g);
-            SiteState<LAT, A> st;
-            SiteScalars sc;
-            collide_site<LAT, QE, DS>(g, shift, c, st, sc, false);
-            val = st.dpost;
-        }
-        halo[s] = val;
-    }
-    __syncthreads();
-
-    Acc acc;
-    const int x = x0 + lx;
-    const bool colok = lx < ncols;
-    const int nb = (hrows + TY - 1) / TY;
-    const int ringw = TX + 2;
-    const int ringrows = 4 * TY;
-
-    auto row_of = [&](int rel) { return y0 - 1 + rel; };
-    auto row_ok = [&](int rel) {
-        const int r = row_of(rel);
-        if (rel >= hrows) return false;
-        if constexpr (BC == kPeriodic) return true;
-        return r >= 0 && r < ny;
-    };
-    auto wrap_row = [&](int r) {
-        if constexpr (BC == kPeriodic) return wrapi(r, ny);
-        return r;
-    };
-
-    A gcur[Q], gnext[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gcur[i] = gnext[i] = A(0);
-    if (colok && row_ok(ly)) gather<LAT, BC>(src, plane, nx, ny, x, wrap_row(row_of(ly)), gcur);
-
-    SiteState<LAT, A> P, N;
-    int clsP = kNodeNone, clsN = kNodeNone;
-    bool nonposP = false, nonposN = false;
-
-    for (int b = 0; b <= nb; ++b) {
-        const int rel = b * TY + ly;
-        if (b < nb) {
-            if (b + 1 < nb && colok && row_ok(rel + TY))
-                gather<LAT, BC>(src, plane, nx, ny, x, wrap_row(row_of(rel + TY)), gnext);
-            const int cr = row_of(rel);
-            const int yy = wrap_row(cr);
-            clsN = (colok && row_ok(rel)) ? node_class<BC>(x, yy, nx, ny) : kNodeNone;
-            const bool owned = clsN != kNodeNone && cr >= y0 && cr < y1;
-            A dsv = A(0);
-            nonposN = false;
-            if (clsN == kNodeFluid) {
+            for (int i = 0; i < Q; ++i) g[i] = gn[i];
+            if (y + 1 < t.y1) gather2d<BC>(src, plane, nx, ny, cl, y + 1, gn);
+            const long long row = (long long)y * nx;
+            const unsigned node = unsigned(row) + unsigned(cl.x);
+            const int cls = node_class<BC>(cl.x, y, nx, ny);
+            if (cls == kNodeFluid) {
+                SiteState<kD2Q9, A> S;
                 SiteScalars sc;
-                collide_site<LAT, QE, DS>(gcur, shift, c, N, sc, owned);
-                dsv = N.dpost;
-                nonposN = sc.nonpos;
-                if (owned) {
-                    acc.moments(sc);
-                    acc.fluid_site(sc, N.dpost);
-                    if (want_ent) {
-                        const double e = entropy_site<LAT>(gcur, shift);
-                        if (isfinite(e)) acc.ent += e;
-                    }
-                    if (x == D.probe_x && yy == D.probe_y) {
-                        const gptr<float> p = to_global<float>(D.probe) + 2 * (step % D.probe_cap);
-                        p[0] = sc.ux;
-                        p[1] = sc.uy;
-                    }
+                collide_site<kD2Q9, QE, DS>(g, shift, c, S, sc, true);
+                acc.moments(sc);
+                acc.fluid_site(sc, S.dpost);
+                if (want_ent) {
+                    const double e = entropy_site<kD2Q9>(g, shift);
+                    if (isfinite(e)) acc.ent += A(e);
                 }
-            } else if (clsN != kNodeNone) {
-                // wall or lid node: keep the arriving populations for the output phase
-#pragma unroll
-                for (int i = 0; i < Q; ++i) N.gs[i] = gcur[i];
-                if (owned) {
-                    SiteScalars sc;
-                    double dr = 0, jx = 0, jy = 0;
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        dr += double(gcur[i]);
-                        jx += L::vx(i) * double(gcur[i]);
-                        jy += L::vy(i) * double(gcur[i]);
-                    }
-                    sc.dr = dr;
-                    sc.jx = jx;
-                    sc.jy = jy;
-                    acc.moments(sc);
+                if (cl.x == D.probe_x && y == D.probe_y) {
+                    const gptr<float> p = to_global<float>(D.probe) + 2 * (step % D.probe_cap);
+                    p[0] = sc.ux;
+                    p[1] = sc.uy;
                 }
-            }
-            const int slot = rel % ringrows;
-            ring[slot * ringw + 1 + lx] = dsv;
-            if (lx == 0 && rel < hrows) {
-                ring[slot * ringw] = halo[rel];
-                ring[slot * ringw + ncols + 1] = halo[hrows + rel];
-            }
-        }
-        __syncthreads();
-        if (b >= 1) {
-            const int relo = rel - TY;
-            const int orow = row_of(relo);
-            if (colok && orow >= y0 && orow < y1 && clsP != kNodeNone) {
-                const unsigned obase = unsigned(orow) * unsigned(nx) + unsigned(x);
                 unsigned mask = 0;
-                A dsrec = A(0);
-                if (clsP == kNodeFluid) {
-                    A med = A(0);
-                    bool has_med = false;
-                    if (D.limiter & kLimMedian) {
-                        const A* rb = ring + ((relo + ringrows - 1) % ringrows) * ringw + lx;
-                        const A* rc = ring + (relo % ringrows) * ringw + lx;
-                        const A* ra = ring + ((relo + 1) % ringrows) * ringw + lx;
-                        const A v00 = rb[0], v01 = rb[1], v02 = rb[2];
-                        const A v10 = rc[0], v11 = rc[1], v12 = rc[2];
-                        const A v20 = ra[0], v21 = ra[1], v22 = ra[2];
-                        has_med = true;
-                        if constexpr (BC == kPeriodic) {
-                            med = median9(v00, v01, v02, v10, v11, v12, v20, v21, v22);
-                        } else {
-                            // Sec. 4.4 stencils: three nodes along a neighbouring wall,
-                            // two inner axis neighbours next to a corner
-                            const bool nl = x == 1, nr = x == nx - 2, nbm = orow == 1, nt = orow == ny - 2;
-                            if ((nl || nr) && (nbm || nt))
-                                med = med3(v11, nl ? v12 : v10, nbm ? v21 : v01);
-                            else if (nl || nr)
-                                med = med3(v01, v11, v21);
-                            else if (nbm || nt)
-                                med = med3(v10, v11, v12);
-                            else
-                                med = median9(v00, v01, v02, v10, v11, v12, v20, v21, v22);
-                        }
-                    }
-                    const A phi = limiter_phi(P.dpost, has_med, med, D, mask);
-                    const A k = phi * c;
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) Store<T>::st(dst + i * plane + obase, P.gs[i] - k * P.d[i]);
-                    if (mask & kMaskTrim) ++acc.trim;
-                    if (mask & kMaskMedian) ++acc.filt;
-                    if (phi < A(1) && isfinite(P.dpost))
-                        acc.lim += double(P.dpost - delta_s_scaled<LAT, DS>(P, shift, c, phi));
-                    if (nonposP) mask |= kMaskNonpos;
-                    dsrec = P.dpost;
-                } else if (clsP == kNodeWall) {
+                const A phi = trim_phi(D, S.dpost, mask);
+                store_limited<T>(dst, plane, row, cl.own, S, phi, c);
+                if (keep_ds) Store<A>::st(dsb + node, S.dpost);
+                if (mask & kMaskTrim) {
+                    ++acc.trim;
+                    if (isfinite(S.dpost)) acc.lim += S.dpost - delta_s_scaled<kD2Q9, DS>(S, shift, c, phi);
+                }
+                if (sc.nonpos) mask |= kMaskNonpos;
+                if (record) {
+                    to_global<unsigned char>(D.mask)[node] = (unsigned char)mask;
+                    to_global<double>(D.dS)[node] = double(S.dpost);
+                }
+            } else {
+                if (cls == kNodeWall) {
                     // bounce-back: every population leaves reversed, no collision
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) Store<T>::st(dst + i * plane + obase, P.gs[L::opp(i)]);
-                    mask = kMaskNotFluid;
+                    for (int i = 0; i < Q; ++i) Store<T>::st(at_bytes(dst + (i * plane + row), cl.own), g[L::opp(i)]);
                 } else {
                     // lid: f*(rho0, (u0, 0)) in shift form
                     A E[Q];
-                    eq_excess<LAT, QE>(A(D.lid_ux), A(0), E);
+                    eq_excess<kD2Q9, QE>(A(D.lid_ux), A(0), E);
                     const A r0 = A(D.rho0);
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
-                        Store<T>::st(dst + i * plane + obase, A(L::w(i)) * ((r0 - shift) + r0 * E[i]));
-                    mask = kMaskNotFluid;
+                        Store<T>::st(at_bytes(dst + (i * plane + row), cl.own), A(L::w(i)) * ((r0 - shift) + r0 * E[i]));
                 }
+                SiteScalars sc;
+                double dr = 0, jx = 0, jy = 0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    dr += double(g[i]);
+                    jx += L::vx(i) * double(g[i]);
+                    jy += L::vy(i) * double(g[i]);
+                }
+                sc.dr = dr;
+                sc.jx = jx;
+                sc.jy = jy;
+                acc.moments(sc);
                 if (record) {
-                    to_global<unsigned char>(D.mask)[obase] = (unsigned char)mask;
-                    to_global<double>(D.dS)[obase] = double(dsrec);
+                    to_global<unsigned char>(D.mask)[node] = (unsigned char)kMaskNotFluid;
+                    to_global<double>(D.dS)[node] = 0.0;
                 }
             }
         }
-        P = N;
-        clsP = clsN;
-        nonposP = nonposN;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
     }
-    store_partial(acc, a.partials + ((long long)a.parity * a.ntiles + xcd_spatial(blockIdx.x, a.ntiles)) * kNStat,
-                  red);
+    store_partial(acc, partial_slot(a, 0, tidx), red);
+}
+
+// Median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the Delta S' plane
+// written by the collision kernel.  Each thread slides a 3x3 window of that
+// plane down its column: one new row (three loads, L1-resident) per node.
+template <class T, int QE, int DS, int BC>
+__global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
+{
+    using A = typename Store<T>::A;
+    constexpr int Q = 9;
+    __shared__ double red[4 * kNStat];
+    const int tidx = tile_of_block(a, 0);
+    const Tile t = a.tiles[tidx];
+    const DomainDev& D = a.dom[t.domain];
+    AccT<A> acc;
+    const int nx = D.nx, ny = D.ny;
+    const int x = t.x0 + int(threadIdx.x);
+    if ((D.limiter & kLimMedian) && x < t.x1) {
+        const long long plane = D.plane;
+        const gptr<const A> dsb = to_global<A>(static_cast<const void*>(D.dsbuf));
+        const A shift = A(D.shift), c = A(D.c);
+        const A dmed = A(D.delta_median);
+        const bool record = a.flags & kFlagRecord;
+        const Cols<T, BC> cl(x, nx, true);
+        int xm, xp;
+        if constexpr (BC == kPeriodic) {
+            xm = x == 0 ? nx - 1 : x - 1;
+            xp = x == nx - 1 ? 0 : x + 1;
+        } else {
+            // cavity: columns off the grid are never part of a fluid stencil
+            xm = x > 0 ? x - 1 : x;
+            xp = x < nx - 1 ? x + 1 : x;
+        }
+        auto wrap_y = [&](int y) {
+            if constexpr (BC == kPeriodic) return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+            return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        };
+        auto load_row = [&](int y, A& l, A& m, A& r) {
+            const long long rr = (long long)wrap_y(y) * nx;
+            l = Store<A>::ld(dsb + (rr + xm));
+            m = Store<A>::ld(dsb + (rr + x));
+            r = Store<A>::ld(dsb + (rr + xp));
+        };
+        // window rows: b (y-1), c (y), n (y+1); columns l, m, r (x-1, x, x+1)
+        A bl, bm, br, cl_, cm, cr, nl, nm, nr;
+        load_row(t.y0 - 1, bl, bm, br);
+        load_row(t.y0, cl_, cm, cr);
+        for (int y = t.y0; y < t.y1; ++y) {
+            load_row(y + 1, nl, nm, nr);
+            if (node_class<BC>(x, y, nx, ny) == kNodeFluid) {
+                const A dc = cm;
+                A med;
+                if constexpr (BC == kPeriodic) {
+                    med = median9(bl, bm, br, cl_, dc, cr, nl, nm, nr);
+                } else {
+                    // three nodes along a neighbouring wall; two inner axis
+                    // neighbours next to a corner; 3x3 elsewhere
+                    const bool wl = x == 1, wr = x == nx - 2, wb = y == 1, wt = y == ny - 2;
+                    if ((wl || wr) && (wb || wt))
+                        med = med3(dc, wl ? cr : cl_, wb ? nm : bm);
+                    else if (wl || wr)
+                        med = med3(bm, dc, nm);
+                    else if (wb || wt)
+                        med = med3(cl_, dc, cr);
+                    else
+                        med = median9(bl, bm, br, cl_, dc, cr, nl, nm, nr);
+                }
+                bool hit;
+                A thr;
+                if (D.median_mode) {
+                    hit = dc > dmed && dc > med;
+                    thr = med;
+                } else {
+                    thr = fmax(med, dmed);
+                    hit = dc > thr;
+                }
+                if (hit) {
+                    ++acc.filt;
+                    unsigned tmask = 0;
+                    const A pt = trim_phi(D, dc, tmask);
+                    const A pm = sqrt_(thr * rcp(dc));
+                    const long long rc = (long long)y * nx;
+                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)kMaskMedian;
+                    if (pm < pt) {
+                        // the filter lowers phi: collide this node again and overwrite
+                        const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
+                        const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
+                        A g[Q];
+                        gather2d<BC>(src, plane, nx, ny, cl, y, g);
+                        SiteState<kD2Q9, A> S;
+                        SiteScalars sc;
+                        collide_site<kD2Q9, QE, DS>(g, shift, c, S, sc, false);
+                        store_limited<T>(dst, plane, rc, cl.own, S, pm, c);
+                        if (isfinite(dc)) {
+                            // limiter entropy production: replace the trimming share
+                            const A before = pt < A(1) ? dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pt) : A(0);
+                            acc.lim += (dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pm)) - before;
+                        }
+                    }
+                }
+            }
+            bl = cl_;
+            bm = cm;
+            br = cr;
+            cl_ = nl;
+            cm = nm;
+            cr = nr;
+        }
+    }
+    store_partial(acc, partial_slot(a, 1, tidx), red);
 }
 
 // D1Q3: each workgroup computes Delta S' at kThreads consecutive sites and
-// updates the kThreads - 2 inner ones (3-point median, Sec. 4.3.2).
+// updates the inner ones (3-point median, Sec. 4.3.2).
+template <int BC, class T>
+__device__ inline void gather1d(gptr<const T> src, long long plane, int nx, int x,
+                                typename Store<T>::A (&g)[3])
+{
+    using L = Lat<kD1Q3>;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int xs = x - L::vx(i);
+        long long off;
+        if constexpr (BC == kPeriodic) {
+            off = i * plane + wrapi(xs, nx);
+        } else {
+            off = (xs >= 0 && xs < nx) ? i * plane + xs : L::opp(i) * plane + x;
+        }
+        g[i] = Store<T>::ld(src + off);
+    }
+}
+
 template <class T, int QE, int DS, int BC>
 __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
 {
     using A = typename Store<T>::A;
     constexpr int LAT = kD1Q3;
-    using L = Lat<LAT>;
-    constexpr int Q = L::Q;
+    constexpr int Q = Lat<LAT>::Q;
     __shared__ A ds[kThreads];
     __shared__ double red[4 * kNStat];
 
-    if (int(blockIdx.x) == a.ntiles) {
+    if (blockIdx.x == 0) {
         reduce_block(a, red);
         return;
     }
-    const Tile t = a.tiles[blockIdx.x];
+    const int tidx = tile_of_block(a, 1);
+    const Tile t = a.tiles[tidx];
     const DomainDev& D = a.dom[t.domain];
     const int tid = threadIdx.x;
     const int nx = D.nx;
@@ -340,7 +417,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
     const int xr = t.x0 - 1 + tid;
     const bool inside = BC == kPeriodic ? true : (xr >= 0 && xr < nx);
     const int x = BC == kPeriodic ? wrapi(xr, nx) : xr;
-    const bool owned = tid >= 1 && tid <= kThreads - 2 && xr < nx && xr < t.x0 + a.tile_w;
+    const bool owned = tid >= 1 && tid <= kThreads - 2 && xr >= t.x0 && xr < t.x1;
 
     Acc acc;
     A g[Q];
@@ -348,7 +425,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
     SiteScalars sc;
     A dsv = A(0);
     if (inside) {
-        gather<LAT, BC>(src, plane, nx, 1, x, 0, g);
+        gather1d<BC>(src, plane, nx, x, g);
         collide_site<LAT, QE, DS>(g, shift, c, S, sc, owned);
         dsv = S.dpost;
         if (owned) {
@@ -384,8 +461,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
             to_global<double>(D.dS)[x] = double(S.dpost);
         }
     }
-    store_partial(acc, a.partials + ((long long)a.parity * a.ntiles + xcd_spatial(blockIdx.x, a.ntiles)) * kNStat,
-                  red);
+    store_partial(acc, partial_slot(a, 0, tidx), red);
 }
 
 // one instantiation per (quasiequilibrium, Delta S form, boundary) in use:
@@ -407,11 +483,13 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
         }                                                                                              \
     } while (0)
 
-hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, int tx, int ty,
+hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, bool median,
                                              hipStream_t s)
 {
-    if (tx * ty != kThreads) return hipErrorInvalidValue;
-    LBM_DISPATCH(k_step2d, 0, 1, dim3(a.ntiles + 1), dim3(tx, ty), 0, s, a);
+    LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !median) return e;
+    LBM_DISPATCH(k_median2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

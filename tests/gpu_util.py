@@ -51,7 +51,7 @@ class Pair:
         fl = L.LBM_RUN_RECORD | (L.LBM_RUN_ENTROPY if entropy else 0) if flags is None else flags
         run = L.Run(storage=storage, flags=fl)
         if tile:
-            run.tile_x, run.tile_y, run.tile_h = tile[0], 256 // tile[0], tile[1]
+            run.tile_h = int(tile)     # rows per D2Q9 wave tile
         with L.lbm_create([dom], run) as ctx:
             self.tile = L.lbm_tile_config(ctx)
             L.lbm_step(ctx, steps)

@@ -114,3 +114,5 @@ def test_mixed_batches_are_rejected(L):
         L.lbm_workspace_bytes([L.Domain(qe=0), L.Domain(qe=1)], L.Run())
     with pytest.raises(L.LbmError):
         L.lbm_workspace_bytes([L.Domain(), L.Domain()], L.Run(tile_x=96))
+    with pytest.raises(L.LbmError):
+        L.lbm_workspace_bytes([L.Domain()], L.Run(tile_h=65))

@@ -34,7 +34,7 @@ def fields_close(pr, rtol=1e-13):
     assert err <= rtol, f"population max rel err {err:.3e}"
 
 
-@pytest.mark.parametrize("tile", [(64, 16), None])
+@pytest.mark.parametrize("tile", [16, None])
 @pytest.mark.parametrize("limiter", [0, 1, 2, 3])
 @pytest.mark.parametrize("ds", [0, 1])
 @pytest.mark.parametrize("qe", [0, 1])
@@ -55,7 +55,7 @@ def test_d2q9_periodic_single_step_fp64(qe, ds, limiter, tile):
 def test_d2q9_limiter_modes_fp64(trim_mode, median_mode):
     f0 = wl.random_populations(9, 130, 90, seed=5, amp=0.05, spike_frac=0.05, spike_amp=0.4)
     pr = Pair(dom2d(nx=130, ny=90, qe=1, limiter=3, trim_mode=trim_mode, median_mode=median_mode,
-                    delta_trim=3e-4, delta_median=2e-5), f0, tile=(128, 32))
+                    delta_trim=3e-4, delta_median=2e-5), f0, tile=32)
     assert_masks_equal(pr)
     assert_ds_close(pr, 1e-12)
     fields_close(pr)
@@ -67,7 +67,7 @@ def test_nonpositive_populations_fp64(ds):
     """Sites with a negative population: Delta S = +inf in the exact form and
     every enabled limiter returns the site to f*."""
     f0 = wl.random_populations(9, 96, 40, seed=21, amp=0.05, spike_frac=0.05, spike_amp=0.4, negative_frac=0.02)
-    pr = Pair(dom2d(nx=96, ny=40, qe=0, ds_form=ds, limiter=3), f0, tile=(64, 16))
+    pr = Pair(dom2d(nx=96, ny=40, qe=0, ds_form=ds, limiter=3), f0, tile=16)
     assert_masks_equal(pr)
     assert_ds_close(pr, 1e-12)
     fields_close(pr)
@@ -84,7 +84,7 @@ def test_cavity_single_step_fp64(qe, limiter):
     f0 = wl.random_populations(9, 100, 100, seed=31 + qe, rho0=2.7, amp=0.05, spike_frac=0.05, spike_amp=0.4)
     d = L.Domain(lattice=D2Q9, nx=100, ny=100, beta=0.97087, qe=qe, limiter=limiter, bc=1, rho0=2.7, lid_ux=0.1,
                  delta_trim=1e-4, delta_median=1e-5)
-    for tile in [(64, 16), None]:
+    for tile in [16, None]:
         pr = Pair(d, f0, tile=tile)
         assert_masks_equal(pr)
         assert_ds_close(pr, 1e-12)
@@ -180,9 +180,9 @@ def test_tile_shapes_give_identical_fields(storage):
     L = lbm()
     f0 = wl.random_populations(9, 300, 70, seed=77, amp=0.05, spike_frac=0.05, spike_amp=0.4)
     outs = []
-    for tile in [(64, 16), (128, 32), (256, 128), (256, 510), (64, 48)]:
+    for tile in [1, 3, 8, 16, 64]:
         d = dom2d(qe=1, ds_form=1 if storage else 0, limiter=3, f_init=f0)
-        run = L.Run(storage=storage, tile_x=tile[0], tile_y=256 // tile[0], tile_h=tile[1], flags=L.LBM_RUN_RECORD)
+        run = L.Run(storage=storage, tile_h=tile, flags=L.LBM_RUN_RECORD)
         with L.lbm_create([d], run) as ctx:
             L.lbm_step(ctx, 5)
             outs.append((L.lbm_get_populations(ctx), L.lbm_limiter_mask(ctx)[0]))
