@@ -4,19 +4,32 @@ Default workload: D2Q9 periodic Taylor-Green vortex plus a seeded random-phase
 perturbation on 4096 x 4096 nodes, FP32 shifted SoA storage, nu = 1e-4,
 entropy trimming and the 3x3 median filter both on (delta = 1e-4),
 polynomial f*, quadratic Delta S, FP64 global reductions every step.  One
-step = one fused launch (free flight, collision, Delta S, both limiters,
-store, reduction of the previous step's partials).
+step = the collision kernel (free flight, moments, f*, over-relaxation,
+Delta S', trimming, store) plus the median kernel (3x3 median of Delta S',
+the filtered nodes collided again), with the previous step's reduction
+folded into the collision launch; steps run as captured HIP graphs.
 
-Prints one JSON line: MLUPS of the whole job, the roofline of the step
-kernel (algorithmic bytes / kernel time vs 8 TB/s HBM), and the FP64 CPU
-oracle timed on the host on a 1024 x 1024 replica of the same workload.
+Prints one JSON line: MLUPS of the whole job, the roofline of the dominant
+kernel (the collision kernel: algorithmic bytes of the step divided by that
+kernel's average duration, measured with HIP events on its stream), the
+roofline of the whole step, and the FP64 CPU oracle timed on the host on a
+1024 x 1024 replica of the same workload.
+
+--variants adds the reduced-precision runs (FP16 / BF16 shifted storage on
+an 8192 x 8192 double shear layer, against FP32 on the same input) and the
+batched ensemble of 256 lid-driven cavities (one launch per step for all of
+them, against the same cavities run one by one).
+
+--summarize-pmc FETCH_CSV WRITE_CSV turns two rocprofv3 --pmc runs of this
+script (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy) into the HBM
+traffic record the roofline reports.
 """
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,9 +38,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d2q9_f32_4096.json")
+BYTES_PER_SITE = {0: 144, 1: 72, 2: 36, 3: 36}     # read Q + write Q populations, D2Q9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide2d_f32_4096.json")
 KERNEL_SOURCES = ["paper_0704_0043_amd/csrc/step.hip", "paper_0704_0043_amd/csrc/lbm_device.h",
                   "paper_0704_0043_amd/csrc/lbm_common.h"]
+DOMINANT = "k_collide2d<float, 0, 1, 0>"
+COPY_BYTES = 1 << 30
 
 
 def kernel_hash() -> str:
@@ -38,7 +54,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def c2_domain(L, wl, n=4096, storage=None):
+def c2_domain(L, wl, n=4096):
     nu = 1e-4
     rho, u = wl.taylor_green(n, u0=0.05, mode=1, perturb=1e-3, seed=wl.DEFAULT_SEED)
     return L.Domain(lattice=L.LBM_D2Q9, nx=n, ny=n, beta=wl.beta_from_nu(nu), qe=L.LBM_QE_POLYNOMIAL,
@@ -87,6 +103,8 @@ def cpu_baseline(wl, seconds=12.0):
 
 
 def load_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    record, or None when the kernel sources changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -97,6 +115,106 @@ def load_traffic():
     return t.get("bytes_per_launch")
 
 
+def copy_calibration(torch, stream, nbytes=COPY_BYTES, reps=3):
+    """A plain elementwise kernel over `nbytes` (reads nbytes, writes nbytes):
+    its FETCH_SIZE / WRITE_SIZE counters give the scale of those counters."""
+    a = torch.rand(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}
+
+
+def variants(torch, L, wl, stream, args):
+    res = {}
+    steps = max(50, args.steps // 4)
+    shear = {}
+    for name, storage in (("f32", L.LBM_F32), ("f16", L.LBM_F16_SHIFT), ("bf16", L.LBM_BF16_SHIFT)):
+        print(f"[bench] variant shear 8192^2 {name}", file=sys.stderr, flush=True)
+        dom = shear_domain(L, wl)
+        with L.lbm_create([dom], L.Run(storage=storage, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
+            ms = time_steps(torch, L, ctx, stream, steps, 16)
+            k1, k2 = L.lbm_kernel_times(ctx, 20)
+        sites = dom.nx * dom.ny
+        b = BYTES_PER_SITE[storage] * sites
+        shear[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
+                       "step_hbm_frac": round(b / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "collide_ms": round(k1, 5), "steps": steps}
+    for name in ("f16", "bf16"):
+        shear[name]["vs_f32"] = round(shear[name]["mlups"] / shear["f32"]["mlups"], 3)
+    res["shear_8192"] = shear
+
+    print("[bench] variant cavity ensemble (256 domains)", file=sys.stderr, flush=True)
+    batch = wl.cavity_batch(256)
+    doms = []
+    for s in batch.specs:
+        rho, u = wl.cavity_rest(s.n, s.n, rho0=1.0)
+        doms.append(L.Domain(lattice=L.LBM_D2Q9, nx=s.n, ny=s.n, beta=s.beta, qe=L.LBM_QE_ENTROPIC,
+                             limiter=L.LBM_LIM_MEDIAN, ds_form=L.LBM_DS_QUADRATIC, bc=L.LBM_BC_CAVITY,
+                             delta_median=1e-3, rho0=1.0, lid_ux=0.1, rho_init=rho, u_init=u, probe=s.probe))
+    bsteps = 200
+    with L.lbm_create(doms, L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=50,
+                                  probe_capacity=bsteps + 64)) as ctx:
+        ms_batch = time_steps(torch, L, ctx, stream, bsteps, 20)
+    ms_single = 0.0
+    for d in doms:
+        with L.lbm_create([d], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=50,
+                                     probe_capacity=bsteps + 64)) as ctx:
+            ms_single += time_steps(torch, L, ctx, stream, bsteps, 20)
+    sites = batch.sites
+    res["cavity_ensemble_256"] = {
+        "sites": sites, "steps": bsteps,
+        "batched_mlups": round(sites * bsteps / (ms_batch * 1e3), 1),
+        "one_by_one_mlups": round(sites * bsteps / (ms_single * 1e3), 1),
+        "speedup": round(ms_single / ms_batch, 2),
+        "step_hbm_frac": round(72 * sites * bsteps / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    return res
+
+
+def summarize_pmc(fetch_csv, write_csv):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dominant kernel,
+    scaled by what the counters read for the calibration kernel (a plain
+    elementwise multiply of COPY_BYTES in, COPY_BYTES out)."""
+    def per_kernel(path, counter):
+        out = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return out
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(d, key, last=None):
+        names = [k for k in d if key in k]
+        if not names:
+            raise SystemExit(f"no dispatch of a kernel matching {key!r}")
+        vals = d[names[0]]
+        return vals[-last:] if last else vals
+
+    cal_f = pick(fetch, "MulFunctor", 3)
+    cal_w = pick(write, "MulFunctor", 3)
+    sf = COPY_BYTES / (sum(cal_f) / len(cal_f))
+    sw = COPY_BYTES / (sum(cal_w) / len(cal_w))
+    k_f = pick(fetch, DOMINANT)
+    k_w = pick(write, DOMINANT)
+    fb = sf * sum(k_f) / len(k_f)
+    wb = sw * sum(k_w) / len(k_w)
+    rec = {"kernel": DOMINANT, "kernel_hash": kernel_hash(), "bytes_per_launch": round(fb + wb),
+           "fetch_bytes": round(fb), "write_bytes": round(wb), "fetch_scale": round(sf, 4),
+           "write_scale": round(sw, 4), "dispatches": [len(k_f), len(k_w)]}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,11 +223,16 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity batch")
-    ap.add_argument("--tile-h", type=int, default=0, help="fixed rows per wave tile instead of autotuning")
+    ap.add_argument("--kernel-steps", type=int, default=50, help="eager steps timed per kernel for the roofline")
+    ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity ensemble")
+    ap.add_argument("--tile-h", type=int, default=0, help="fixed rows per tile instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain device copy of 1 GiB (known bytes) to scale HBM counters")
+                    help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -134,13 +257,15 @@ def main():
     tile = L.lbm_tile_config(ctx)
     print(f"[bench] tile {tile}; warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
     ms = time_steps(torch, L, ctx, stream, args.steps, args.warmup)
+    print(f"[bench] per-kernel timing over {args.kernel_steps} eager steps", file=sys.stderr, flush=True)
+    k1_ms, k2_ms = L.lbm_kernel_times(ctx, args.kernel_steps)
     stats = L.lbm_entropy_stats(ctx)
     sites = n * n
     ms_step = ms / args.steps
     mlups = sites * args.steps / (ms * 1e3)
-    bytes_per_site = 2 * 9 * 4
-    bytes_launch = bytes_per_site * sites
-    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    alg_bytes = BYTES_PER_SITE[L.LBM_F32] * sites          # per step = per collision launch
+    achieved = alg_bytes / (k1_ms * 1e-3) / 1e9
+    step_achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     traffic = load_traffic()
     out = {
         "metric": "MLUPS + % HBM roofline, limited D2Q9 step; batched/low-precision vs plain FP32",
@@ -166,6 +291,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
         },
+        "kernels": {"dominant": DOMINANT, "collide_ms": round(k1_ms, 5), "median_ms": round(k2_ms, 5),
+                    "algorithmic_bytes_per_launch": alg_bytes},
+        "step_roofline": {"achieved": round(step_achieved, 1), "frac": round(step_achieved / HBM_PEAK_GBS, 4),
+                          "unit": "GB/s"},
         "stats": {"mass": stats["mass"], "n_trimmed": stats["n_trimmed"], "n_filtered": stats["n_filtered"],
                   "max_dS": stats["max_dS"], "n_nonfinite": stats["n_nonfinite"]},
     }
@@ -178,33 +307,6 @@ def main():
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-
-
-def copy_calibration(torch, stream, nbytes=1 << 30, reps=3):
-    """A plain device-to-device copy of `nbytes` (read nbytes, write nbytes):
-    its FETCH_SIZE / WRITE_SIZE counters give the scale of those counters."""
-    a = torch.ones(nbytes // 4, device="cuda")
-    b = torch.empty_like(a)
-    with torch.cuda.stream(stream):
-        for _ in range(reps):
-            b.copy_(a)
-    torch.cuda.synchronize()
-    return {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}
-
-
-def variants(torch, L, wl, stream, args):
-    res = {}
-    steps = max(50, args.steps // 4)
-    for name, storage in (("f32_8192", L.LBM_F32), ("f16_8192", L.LBM_F16_SHIFT), ("bf16_8192", L.LBM_BF16_SHIFT)):
-        print(f"[bench] variant {name}", file=sys.stderr, flush=True)
-        dom = shear_domain(L, wl)
-        with L.lbm_create([dom], L.Run(storage=storage, stream=stream.cuda_stream)) as ctx:
-            ms = time_steps(torch, L, ctx, stream, steps, 16)
-        sites = dom.nx * dom.ny
-        b = 2 * 9 * L.STORAGE_BYTES[storage]
-        res[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
-                     "hbm_frac": round(b * sites / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "steps": steps}
-    return res
 
 
 if __name__ == "__main__":

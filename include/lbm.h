@@ -197,6 +197,15 @@ LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max
 /* Tile shape in use (after autotuning): columns, 1, rows (D1Q3: 254, 1, 1). */
 LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
 
+/* sync; profiling aid outside the method.  Advances the state by n_steps
+ * (1..4096) like lbm_step, but launches every step eagerly (no graph) with
+ * HIP events around each kernel on the context's stream, and writes the
+ * average duration in milliseconds of the collision kernel to ms[0] and of
+ * the median kernel to ms[1] (0 when no median pass runs).  ms is a
+ * caller-owned host array of 2 doubles.  LBM_EINVAL for a bad count or a
+ * NULL pointer. */
+LBM_API int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms);
+
 /* Release everything the context owns.  NULL is accepted. */
 LBM_API void lbm_destroy(lbm_ctx* ctx);
 

@@ -5,22 +5,22 @@
 
 namespace lbm {
 
-hipError_t launch_step2d_st0(int, int, int, const StepArgs&, bool, hipStream_t);
-hipError_t launch_step2d_st1(int, int, int, const StepArgs&, bool, hipStream_t);
-hipError_t launch_step2d_st2(int, int, int, const StepArgs&, bool, hipStream_t);
-hipError_t launch_step2d_st3(int, int, int, const StepArgs&, bool, hipStream_t);
+hipError_t launch_step2d_st0(int, int, int, const StepArgs&, int, hipStream_t);
+hipError_t launch_step2d_st1(int, int, int, const StepArgs&, int, hipStream_t);
+hipError_t launch_step2d_st2(int, int, int, const StepArgs&, int, hipStream_t);
+hipError_t launch_step2d_st3(int, int, int, const StepArgs&, int, hipStream_t);
 hipError_t launch_step1d_st0(int, int, int, const StepArgs&, hipStream_t);
 hipError_t launch_step1d_st1(int, int, int, const StepArgs&, hipStream_t);
 hipError_t launch_step1d_st2(int, int, int, const StepArgs&, hipStream_t);
 hipError_t launch_step1d_st3(int, int, int, const StepArgs&, hipStream_t);
 
-hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, bool median, hipStream_t s)
+hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s)
 {
     switch (storage) {
-    case kF64: return launch_step2d_st0(qe, ds, bc, a, median, s);
-    case kF32: return launch_step2d_st1(qe, ds, bc, a, median, s);
-    case kF16: return launch_step2d_st2(qe, ds, bc, a, median, s);
-    case kBF16: return launch_step2d_st3(qe, ds, bc, a, median, s);
+    case kF64: return launch_step2d_st0(qe, ds, bc, a, kernel, s);
+    case kF32: return launch_step2d_st1(qe, ds, bc, a, kernel, s);
+    case kF16: return launch_step2d_st2(qe, ds, bc, a, kernel, s);
+    case kBF16: return launch_step2d_st3(qe, ds, bc, a, kernel, s);
     }
     return hipErrorInvalidValue;
 }

@@ -331,14 +331,23 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     return a;
 }
 
-int launch_one(lbm_ctx* ctx, int parity)
+// One step of every domain.  With `ev` (three events) the launches are
+// bracketed for per-kernel timing: ev[0] | collision | ev[1] | median | ev[2].
+int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
 {
     const StepArgs a = step_args(ctx, parity);
-    hipError_t e;
-    if (ctx->lattice == LBM_D2Q9)
-        e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->median_pass, ctx->stream);
-    else
-        e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
+    hipError_t e = hipSuccess;
+    if (ev) e = hipEventRecord(ev[0], ctx->stream);
+    if (e == hipSuccess) {
+        if (ctx->lattice == LBM_D2Q9)
+            e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 0, ctx->stream);
+        else
+            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
+    if (e == hipSuccess && ctx->lattice == LBM_D2Q9 && ctx->median_pass)
+        e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], ctx->stream);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return LBM_OK;
 }
@@ -770,6 +779,41 @@ int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_
     if (tile_x) *tile_x = d2 ? kThreads : k1DWidth;
     if (tile_y) *tile_y = 1;
     if (tile_h) *tile_h = d2 ? ctx->th : 1;
+    return LBM_OK;
+}
+
+int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
+{
+    if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
+    if (!ms || n_steps < 1 || n_steps > 4096) return fail(ctx, LBM_EINVAL, "need 1 <= n_steps <= 4096 and ms");
+    std::vector<hipEvent_t> ev(size_t(3 * n_steps), nullptr);
+    int rc = LBM_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            rc = fail(ctx, LBM_EDEVICE, "hipEventCreate failed");
+            break;
+        }
+    for (int64_t k = 0; k < n_steps && rc == LBM_OK; ++k) {
+        rc = launch_one(ctx, int(ctx->steps_done % 2), &ev[size_t(3 * k)]);
+        if (rc == LBM_OK) ++ctx->steps_done;
+    }
+    double t[2] = {0, 0};
+    if (rc == LBM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(ctx, LBM_EDEVICE, "sync failed");
+    for (int64_t k = 0; k < n_steps && rc == LBM_OK; ++k)
+        for (int j = 0; j < 2; ++j) {
+            float x = 0;
+            if (hipEventElapsedTime(&x, ev[size_t(3 * k + j)], ev[size_t(3 * k + j + 1)]) != hipSuccess) {
+                rc = fail(ctx, LBM_EDEVICE, "hipEventElapsedTime failed");
+                break;
+            }
+            t[j] += x;
+        }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    ms[0] = t[0] / double(n_steps);
+    ms[1] = (ctx->lattice == LBM_D2Q9 && ctx->median_pass) ? t[1] / double(n_steps) : 0.0;
     return LBM_OK;
 }
 

@@ -79,7 +79,8 @@ struct StepArgs {
 };
 
 // Launchers (one per storage type / lattice), defined in the .hip files.
-hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, bool median, hipStream_t s);
+// kernel 0: collision kernel; kernel 1: median kernel (after kernel 0)
+hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
 hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);
 hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u, double* f, int nx, int ny,

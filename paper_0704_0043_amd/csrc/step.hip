@@ -261,8 +261,44 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
 }
 
 // Median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the Delta S' plane
-// written by the collision kernel.  Each thread slides a 3x3 window of that
-// plane down its column: one new row (three loads, L1-resident) per node.
+// written by the collision kernel.  Each thread walks down its column in
+// chunks of kMedChunk rows: the loads of a whole chunk (three per row, L1- and
+// L2-resident for the neighbouring columns) are issued together, then the
+// medians of the chunk are taken from registers.  The rare nodes the filter
+// hits are handled after the chunk, one at a time.
+constexpr int kMedChunk = 16;
+
+// median threshold of a fluid node from its window (rows b, c, n = y-1, y, y+1;
+// columns l, m, r = x-1, x, x+1); returns whether the filter hits the node
+template <int BC, class A>
+__device__ __forceinline__ bool median_hit(const DomainDev& D, int x, int y, int nx, int ny, const A (&b)[3],
+                                           const A (&c)[3], const A (&n)[3], A& thr)
+{
+    A med;
+    if constexpr (BC == kPeriodic) {
+        med = median9(b[0], b[1], b[2], c[0], c[1], c[2], n[0], n[1], n[2]);
+    } else {
+        // three nodes along a neighbouring wall; two inner axis neighbours
+        // next to a corner; 3x3 elsewhere
+        const bool wl = x == 1, wr = x == nx - 2, wb = y == 1, wt = y == ny - 2;
+        if ((wl || wr) && (wb || wt))
+            med = med3(c[1], wl ? c[2] : c[0], wb ? n[1] : b[1]);
+        else if (wl || wr)
+            med = med3(b[1], c[1], n[1]);
+        else if (wb || wt)
+            med = med3(c[0], c[1], c[2]);
+        else
+            med = median9(b[0], b[1], b[2], c[0], c[1], c[2], n[0], n[1], n[2]);
+    }
+    const A dc = c[1], dmed = A(D.delta_median);
+    if (D.median_mode) {
+        thr = med;
+        return dc > dmed && dc > med;
+    }
+    thr = fmax(med, dmed);
+    return dc > thr;
+}
+
 template <class T, int QE, int DS, int BC>
 __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
 {
@@ -279,9 +315,7 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
         const long long plane = D.plane;
         const gptr<const A> dsb = to_global<A>(static_cast<const void*>(D.dsbuf));
         const A shift = A(D.shift), c = A(D.c);
-        const A dmed = A(D.delta_median);
         const bool record = a.flags & kFlagRecord;
-        const Cols<T, BC> cl(x, nx, true);
         int xm, xp;
         if constexpr (BC == kPeriodic) {
             xm = x == 0 ? nx - 1 : x - 1;
@@ -291,80 +325,76 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
             xm = x > 0 ? x - 1 : x;
             xp = x < nx - 1 ? x + 1 : x;
         }
-        auto wrap_y = [&](int y) {
-            if constexpr (BC == kPeriodic) return y < 0 ? y + ny : (y >= ny ? y - ny : y);
-            return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        // rows y0-1 .. y1 are read; y1 <= ny, so one wrap keeps them in range
+        auto load_row = [&](int y, A (&r)[3]) {
+            int yy;
+            if constexpr (BC == kPeriodic)
+                yy = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+            else
+                yy = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+            const long long rr = (long long)yy * nx;
+            r[0] = Store<A>::ld(dsb + (rr + xm));
+            r[1] = Store<A>::ld(dsb + (rr + x));
+            r[2] = Store<A>::ld(dsb + (rr + xp));
         };
-        auto load_row = [&](int y, A& l, A& m, A& r) {
-            const long long rr = (long long)wrap_y(y) * nx;
-            l = Store<A>::ld(dsb + (rr + xm));
-            m = Store<A>::ld(dsb + (rr + x));
-            r = Store<A>::ld(dsb + (rr + xp));
-        };
-        // window rows: b (y-1), c (y), n (y+1); columns l, m, r (x-1, x, x+1)
-        A bl, bm, br, cl_, cm, cr, nl, nm, nr;
-        load_row(t.y0 - 1, bl, bm, br);
-        load_row(t.y0, cl_, cm, cr);
-        for (int y = t.y0; y < t.y1; ++y) {
-            load_row(y + 1, nl, nm, nr);
-            if (node_class<BC>(x, y, nx, ny) == kNodeFluid) {
-                const A dc = cm;
-                A med;
-                if constexpr (BC == kPeriodic) {
-                    med = median9(bl, bm, br, cl_, dc, cr, nl, nm, nr);
-                } else {
-                    // three nodes along a neighbouring wall; two inner axis
-                    // neighbours next to a corner; 3x3 elsewhere
-                    const bool wl = x == 1, wr = x == nx - 2, wb = y == 1, wt = y == ny - 2;
-                    if ((wl || wr) && (wb || wt))
-                        med = med3(dc, wl ? cr : cl_, wb ? nm : bm);
-                    else if (wl || wr)
-                        med = med3(bm, dc, nm);
-                    else if (wb || wt)
-                        med = med3(cl_, dc, cr);
-                    else
-                        med = median9(bl, bm, br, cl_, dc, cr, nl, nm, nr);
-                }
-                bool hit;
+        // w[k] holds row yb - 1 + k of the current chunk
+        A w[kMedChunk + 2][3];
+        load_row(t.y0 - 1, w[0]);
+        load_row(t.y0, w[1]);
+        for (int yb = t.y0; yb < t.y1; yb += kMedChunk) {
+#pragma unroll
+            for (int k = 0; k < kMedChunk; ++k)
+                if (yb + k + 1 <= t.y1) load_row(yb + k + 1, w[k + 2]);
+            unsigned hits = 0;
+#pragma unroll
+            for (int k = 0; k < kMedChunk; ++k) {
+                const int y = yb + k;
                 A thr;
-                if (D.median_mode) {
-                    hit = dc > dmed && dc > med;
-                    thr = med;
-                } else {
-                    thr = fmax(med, dmed);
-                    hit = dc > thr;
-                }
-                if (hit) {
-                    ++acc.filt;
-                    unsigned tmask = 0;
-                    const A pt = trim_phi(D, dc, tmask);
-                    const A pm = sqrt_(thr * rcp(dc));
-                    const long long rc = (long long)y * nx;
-                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)kMaskMedian;
-                    if (pm < pt) {
-                        // the filter lowers phi: collide this node again and overwrite
-                        const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
-                        const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
-                        A g[Q];
-                        gather2d<BC>(src, plane, nx, ny, cl, y, g);
-                        SiteState<kD2Q9, A> S;
-                        SiteScalars sc;
-                        collide_site<kD2Q9, QE, DS>(g, shift, c, S, sc, false);
-                        store_limited<T>(dst, plane, rc, cl.own, S, pm, c);
-                        if (isfinite(dc)) {
-                            // limiter entropy production: replace the trimming share
-                            const A before = pt < A(1) ? dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pt) : A(0);
-                            acc.lim += (dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pm)) - before;
-                        }
+                if (y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid &&
+                    median_hit<BC>(D, x, y, nx, ny, w[k], w[k + 1], w[k + 2], thr))
+                    hits |= 1u << k;
+            }
+            // hit nodes: reload the window (cache-resident), take the same
+            // decision again, and collide again if the filter lowers phi
+            while (hits) {
+                const int k = __builtin_ctz(hits);
+                hits &= hits - 1;
+                const int y = yb + k;
+                A b[3], m[3], n[3], thr;
+                load_row(y - 1, b);
+                load_row(y, m);
+                load_row(y + 1, n);
+                median_hit<BC>(D, x, y, nx, ny, b, m, n, thr);
+                const A dc = m[1];
+                ++acc.filt;
+                unsigned tmask = 0;
+                const A pt = trim_phi(D, dc, tmask);
+                const A pm = sqrt_(thr * rcp(dc));
+                const long long rc = (long long)y * nx;
+                if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)kMaskMedian;
+                if (pm < pt) {
+                    // the filter lowers phi: collide this node again and overwrite
+                    const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
+                    const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
+                    const Cols<T, BC> cl(x, nx, true);
+                    A g[Q];
+                    gather2d<BC>(src, plane, nx, ny, cl, y, g);
+                    SiteState<kD2Q9, A> S;
+                    SiteScalars sc;
+                    collide_site<kD2Q9, QE, DS>(g, shift, c, S, sc, false);
+                    store_limited<T>(dst, plane, rc, cl.own, S, pm, c);
+                    if (isfinite(dc)) {
+                        // limiter entropy production: replace the trimming share
+                        const A before = pt < A(1) ? dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pt) : A(0);
+                        acc.lim += (dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pm)) - before;
                     }
                 }
             }
-            bl = cl_;
-            bm = cm;
-            br = cr;
-            cl_ = nl;
-            cm = nm;
-            cr = nr;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                w[0][q] = w[kMedChunk][q];
+                w[1][q] = w[kMedChunk + 1][q];
+            }
         }
     }
     store_partial(acc, partial_slot(a, 1, tidx), red);
@@ -483,13 +513,13 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
         }                                                                                              \
     } while (0)
 
-hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, bool median,
+hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, int kernel,
                                              hipStream_t s)
 {
-    LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !median) return e;
-    LBM_DISPATCH(k_median2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
+    if (kernel == 0)
+        LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
+    else
+        LBM_DISPATCH(k_median2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -100,6 +100,7 @@ SIGNATURES = {
     "lbm_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_limiter_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8), _dp]),
+    "lbm_kernel_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "lbm_probe_trace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "lbm_tile_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
@@ -335,6 +336,14 @@ def lbm_tile_config(ctx: Context):
     tx, ty, th = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib().lbm_tile_config(ctx.handle, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(th)), ctx.handle)
     return tx.value, ty.value, th.value
+
+
+def lbm_kernel_times(ctx: Context, n_steps: int):
+    """Advance n_steps eagerly with events around each kernel; returns the
+    average (collision, median) kernel durations in milliseconds."""
+    ms = (ctypes.c_double * 2)()
+    _check(lib().lbm_kernel_times(ctx.handle, int(n_steps), ms), ctx.handle)
+    return ms[0], ms[1]
 
 
 def lbm_destroy(ctx: Context) -> None:

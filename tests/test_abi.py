@@ -90,6 +90,12 @@ def test_host_only_entry_points(L):
     n = L.lbm_workspace_bytes([L.Domain(nx=128, ny=64)], L.Run(storage=L.LBM_F32))
     # two FP32 population buffers of 9 planes at least
     assert n >= 2 * 9 * 128 * 64 * 4
+    # entry points taking a context reject NULL without touching a device
+    lib = L.lib()
+    ms = (L.ctypes.c_double * 2)()
+    assert lib.lbm_kernel_times(None, 4, ms) == L.LBM_EINVAL
+    assert lib.lbm_step(None, 1) == L.LBM_EINVAL
+    assert lib.lbm_tile_config(None, None, None, None) == L.LBM_EINVAL
 
 
 @pytest.mark.parametrize("bad", [
