@@ -250,12 +250,28 @@ __device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift,
     A inv = rcp(rho);
     A ux = jx * inv, uy = jy * inv;
     A E[Q];
-    eq_excess<LAT, QE>(ux, uy, E);
+    if constexpr (QE == kPoly) {
+        // rho E_i = 3 v_i.j + rho (9 (v_i.u)^2 / 2 - 3 u^2 / 2): the linear
+        // term is taken from j itself, so the momentum of f* is j up to the
+        // rounding of sums, whatever the rounding of u = j / rho (a biased
+        // reciprocal would otherwise feed a drift of momentum every step)
+        const A base = A(-1.5) * (ux * ux + uy * uy);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const A cu = A(L::vx(i)) * ux + A(L::vy(i)) * uy;
+            const A cj = A(L::vx(i)) * jx + A(L::vy(i)) * jy;
+            E[i] = A(3) * cj + rho * (base + A(4.5) * cu * cu);
+        }
+    } else {
+        eq_excess<LAT, QE>(ux, uy, E);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) E[i] = rho * E[i];
+    }
     A fs[Q];
     bool fs_ok = true, pre_ok = true, post_ok = true;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        o.gs[i] = A(L::w(i)) * (dr + rho * E[i]);
+        o.gs[i] = A(L::w(i)) * (dr + E[i]);
         fs[i] = A(L::w(i)) * shift + o.gs[i];
         o.d[i] = g[i] - o.gs[i];
         fs_ok &= fs[i] > A(0);

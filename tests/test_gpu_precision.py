@@ -52,6 +52,11 @@ def run_both(dom, steps, storage, record=False):
     return out, f
 
 
+def run_f0(dom):
+    o = orc()
+    return o.init_equilibrium(oracle_params(dom), dom.rho_init, dom.u_init)
+
+
 def test_fp32_taylor_green_replica():
     """The headline workload (periodic Taylor-Green plus random-phase
     perturbation, nu = 1e-4, trimming and median filter, polynomial f*,
@@ -67,7 +72,10 @@ def test_fp32_taylor_green_replica():
     assert r["rho"] <= 1e-5 and r["u"] <= 1e-5
     assert r["mask_mismatch"] == 0
     assert r["stats"]["n_trimmed"] == r["oracle"]["n_trimmed"]
-    assert r["stats"]["mass"] == pytest.approx(r["oracle"]["mass"], rel=1e-9)
+    # mass moves only by the rounding of the stored shifts: at most
+    # n Q u_r max|g| relative over n steps
+    g = np.abs(run_f0(dom) - W9[:, None, None])
+    assert r["stats"]["mass"] == pytest.approx(r["oracle"]["mass"], rel=200 * 9 * 2.0 ** -24 * g.max())
 
 
 def test_fp32_limited_random_single_step():
