@@ -17,6 +17,12 @@
  *   - median entropy filter: Sec. 3.5, cavity stencil rule of Sec. 4.4
  *   - free flight: Sec. 2; bounce-back walls and constant lid: Sec. 4.4.1
  *
+ * Parity unpinned: the near-wall and corner median stencils of the cavity
+ * (Sec. 4.4 reading: three nodes along a neighbouring wall, self plus two inner
+ * axis neighbours next to a corner) and the lid density rho0 have no closed
+ * form or printed value to check against; only the vortex centres of Table 1
+ * (to within a node or two) constrain them.
+ *
  * Layout: populations f[i*n + y*nx + x], n = nx*ny, x fastest (ny = 1 for
  * D1Q3).  The state passed in and out of orc_step is the post-streaming
  * (pre-collision) state f(x, t) of eq. (lbgkLB).
