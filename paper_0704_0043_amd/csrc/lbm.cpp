@@ -52,11 +52,13 @@ struct DomainHost {
     bool dsbuf = false;
     double shift = 0;
     int tile_first = 0, tile_count = 0;
+    int row_first = 0, row_count = 0;
 };
 
 struct Layout {
     size_t off_dom = 0, off_tiles = 0, off_partials = 0, off_counter = 0, off_stage = 0, total = 0;
-    int max_tiles = 0;
+    size_t off_rows = 0, off_rowpart = 0;
+    int max_tiles = 0, nrows = 0;
     size_t max_n = 0;
 };
 
@@ -81,10 +83,13 @@ struct lbm_ctx {
     std::string err;
     std::vector<double> tune_log;   // (rows per tile, us per step) pairs
     std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
+    std::vector<Tile> rows_host;
     std::vector<DomainDev> dom_host;
 
     DomainDev* d_dom() const { return reinterpret_cast<DomainDev*>(ws + lay.off_dom); }
     Tile* d_tiles() const { return reinterpret_cast<Tile*>(ws + lay.off_tiles); }
+    Tile* d_rows() const { return reinterpret_cast<Tile*>(ws + lay.off_rows); }
+    double* d_rowpart() const { return reinterpret_cast<double*>(ws + lay.off_rowpart); }
     double* d_partials() const { return reinterpret_cast<double*>(ws + lay.off_partials); }
     long long* d_counter() const { return reinterpret_cast<long long*>(ws + lay.off_counter); }
     double* d_stage() const { return reinterpret_cast<double*>(ws + lay.off_stage); }
@@ -190,6 +195,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     const int cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;
     size_t off = 0;
     L.max_tiles = 0;
+    L.nrows = 0;
     L.max_n = 0;
     dh.resize(nd);
     for (int k = 0; k < nd; ++k) {
@@ -225,6 +231,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         const int tiles = h.d.lattice == LBM_D2Q9 ? strips_of(h.d.nx) * ((h.d.ny + min_h - 1) / min_h)
                                                   : (h.d.nx + k1DWidth - 1) / k1DWidth;
         L.max_tiles += tiles;
+        if (h.d.lattice == LBM_D2Q9) L.nrows += strips_of(h.d.nx) * h.d.ny;
         L.max_n = std::max(L.max_n, h.n);
     }
     L.off_dom = off;
@@ -232,7 +239,11 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     L.off_tiles = off;
     off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
     L.off_partials = off;
-    off = align_up(off + size_t(4) * L.max_tiles * kNStat * sizeof(double), kAlign);
+    off = align_up(off + size_t(2) * L.max_tiles * kNStat * sizeof(double), kAlign);
+    L.off_rows = off;
+    off = align_up(off + size_t(L.nrows) * sizeof(Tile), kAlign);
+    L.off_rowpart = off;
+    off = align_up(off + size_t(L.nrows) * kNStat * sizeof(double), kAlign);
     L.off_counter = off;
     off = align_up(off + 2 * sizeof(long long), kAlign);
     L.off_stage = off;
@@ -253,16 +264,34 @@ std::vector<Tile> build_tiles(lbm_ctx* ctx, int th)
         h.tile_first = int(spatial.size());
         const int nx = h.d.nx, ny = h.d.ny;
         if (ctx->lattice == LBM_D2Q9) {
-            for (int y0 = 0; y0 < ny; y0 += th)
+            const int chunks = (ny + th - 1) / th;
+            for (int r = 0; r < chunks; ++r)
                 for (int x0 = 0; x0 < nx; x0 += kThreads)
-                    spatial.push_back(Tile{int(k), x0, std::min(x0 + kThreads, nx), y0, std::min(y0 + th, ny), 0, 0, 0});
+                    spatial.push_back(Tile{int(k), x0, std::min(x0 + kThreads, nx), r * th, std::min(r * th + th, ny),
+                                           r, chunks, (ny - r + chunks - 1) / chunks});
         } else {
             for (int x0 = 0; x0 < nx; x0 += k1DWidth)
-                spatial.push_back(Tile{int(k), x0, std::min(x0 + k1DWidth, nx), 0, 1, 0, 0, 0});
+                spatial.push_back(Tile{int(k), x0, std::min(x0 + k1DWidth, nx), 0, 1, 0, 1, 1});
         }
         h.tile_count = int(spatial.size()) - h.tile_first;
     }
     return spatial;
+}
+
+// D2Q9 row segments of kThreads columns, row-major within each domain: the
+// collision kernel runs one workgroup per segment in this order.
+void build_rows(lbm_ctx* ctx)
+{
+    ctx->rows_host.clear();
+    if (ctx->lattice != LBM_D2Q9) return;
+    for (size_t k = 0; k < ctx->dom.size(); ++k) {
+        DomainHost& h = ctx->dom[k];
+        h.row_first = int(ctx->rows_host.size());
+        for (int y = 0; y < h.d.ny; ++y)
+            for (int x0 = 0; x0 < h.d.nx; x0 += kThreads)
+                ctx->rows_host.push_back(Tile{int(k), x0, std::min(x0 + kThreads, h.d.nx), y, y + 1, y, 1, 1});
+        h.row_count = int(ctx->rows_host.size()) - h.row_first;
+    }
 }
 
 int upload_domains(lbm_ctx* ctx)
@@ -294,6 +323,9 @@ int upload_domains(lbm_ctx* ctx)
         d.dS = (ctx->flags & LBM_RUN_RECORD) ? reinterpret_cast<double*>(ctx->ws + h.off_ds) : nullptr;
         d.tile_first = h.tile_first;
         d.tile_count = h.tile_count;
+        d.strips = strips_of(h.d.nx);
+        d.row_first = h.row_first;
+        d.row_count = h.row_count;
         d.stats = reinterpret_cast<double*>(ctx->ws + h.off_stats);
         d.dsbuf = h.dsbuf ? ctx->ws + h.off_dsbuf : nullptr;
     }
@@ -323,7 +355,9 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.tiles = ctx->d_tiles();
     a.ntiles = ctx->ntiles;
     a.ndomains = int(ctx->dom.size());
-    a.median_pass = ctx->median_pass ? 1 : 0;
+    a.rows = ctx->d_rows();
+    a.nrows = ctx->lay.nrows;
+    a.rowpart = ctx->d_rowpart();
     a.parity = parity;
     a.flags = ctx->flags & (LBM_RUN_RECORD | LBM_RUN_ENTROPY);
     a.partials = ctx->d_partials();
@@ -345,7 +379,7 @@ int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
             e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
-    if (e == hipSuccess && ctx->lattice == LBM_D2Q9 && ctx->median_pass)
+    if (e == hipSuccess && ctx->lattice == LBM_D2Q9)
         e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], ctx->stream);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -614,6 +648,14 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("init: ") + hipGetErrorString(e)));
     }
+    build_rows(ctx);
+    if (int(ctx->rows_host.size()) != ctx->lay.nrows)
+        return bail(fail(nullptr, LBM_EINVAL, "row table size mismatch"));
+    if (!ctx->rows_host.empty()) {
+        e = hipMemcpyAsync(ctx->d_rows(), ctx->rows_host.data(), ctx->rows_host.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("rows: ") + hipGetErrorString(e)));
+    }
     rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run->tile_h) : set_tiles(ctx, 1);
     if (rc) {
         g_err = ctx->err;
@@ -813,7 +855,7 @@ int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     ms[0] = t[0] / double(n_steps);
-    ms[1] = (ctx->lattice == LBM_D2Q9 && ctx->median_pass) ? t[1] / double(n_steps) : 0.0;
+    ms[1] = ctx->lattice == LBM_D2Q9 ? t[1] / double(n_steps) : 0.0;
     return LBM_OK;
 }
 

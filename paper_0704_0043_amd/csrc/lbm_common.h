@@ -44,6 +44,8 @@ struct DomainDev {
     unsigned char* mask;    // [ny*nx] when recording
     double* dS;             // [ny*nx] when recording
     int tile_first, tile_count;   // this domain's range in the tile table
+    int strips;                   // D2Q9: column strips of kThreads columns
+    int row_first, row_count;     // D2Q9: this domain's range in the row table
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
     void* dsbuf;            // [ny*nx] Delta S' of the last collision (arithmetic type), median only
 };
@@ -61,25 +63,32 @@ __host__ __device__ inline int xcd_spatial(int b, int T)
     return x * q + (x < r ? x : r) + j;
 }
 
-// one work item (one workgroup): columns [x0, x1), rows [y0, y1) of one domain
+// One work item (one workgroup) over columns [x0, x1) of one domain.  The
+// median kernel takes the consecutive rows [y0, y1); the collision kernel the
+// rows ys, ys + ystep, ..., (yn of them).  With ystep = the number of row
+// chunks, the collision tiles that run together all work on one narrow band
+// of rows at a time, which keeps the DRAM pages they touch few and the rows
+// their neighbours pull from in L2.
 struct Tile {
-    int domain, x0, x1, y0, y1, pad0, pad1, pad2;
+    int domain, x0, x1, y0, y1, ys, ystep, yn;
 };
 
 struct StepArgs {
     const DomainDev* dom;
     const Tile* tiles;      // spatial order (domain, row chunk, column strip)
-    int ntiles;             // the collision grid has ntiles + 1 blocks; block 0 reduces
+    int ntiles;             // the second D2Q9 pass (and D1Q3) has one workgroup per tile
     int ndomains;
     int parity;             // read buf[parity], write buf[1 - parity]
     unsigned flags;
-    double* partials;       // [2 parities][2 kernels][ntiles][kNStat], by spatial tile
-    int median_pass;        // 1 if the median kernel runs after the collision kernel
+    double* partials;       // [2 parities][ntiles][kNStat]: FP64 stats of each tile
+    const Tile* rows;       // D2Q9 row segments in row-major order, one per collision workgroup
+    int nrows;              // the collision grid has nrows + 1 blocks; block 0 reduces
+    double* rowpart;        // [nrows][kNStat]: collision partials, summed by the second pass
     long long* counter;     // [2] step index by parity
 };
 
 // Launchers (one per storage type / lattice), defined in the .hip files.
-// kernel 0: collision kernel; kernel 1: median kernel (after kernel 0)
+// kernel 0: collision kernel; kernel 1: median filter and tile reduction (after kernel 0)
 hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
 hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);

@@ -68,6 +68,30 @@ __device__ inline gptr<T> to_global(void* p) { return (gptr<T>)p; }
 template <class T>
 __device__ inline gptr<const T> to_global(const void* p) { return (gptr<const T>)p; }
 
+// Value held by the lane D = -1 (left) or +1 (right) positions away in the
+// same wave, by a DPP wave shift (wave_shr:1 = 0x138 moves lane i-1 to lane i,
+// wave_shl:1 = 0x130 moves lane i+1 to lane i).  The lane at the end of the
+// wave keeps its own value; callers replace it.  Convergent: every active lane
+// must execute it.
+template <int D>
+__device__ __forceinline__ int lane_shift_i(int v)
+{
+    static_assert(D == 1 || D == -1, "neighbour lanes only");
+    return __builtin_amdgcn_update_dpp(v, v, D < 0 ? 0x138 : 0x130, 0xF, 0xF, false);
+}
+template <int D>
+__device__ __forceinline__ float lane_shift(float v)
+{
+    return __builtin_bit_cast(float, lane_shift_i<D>(__builtin_bit_cast(int, v)));
+}
+template <int D>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = lane_shift_i<D>(int(b & 0xffffffffll)), hi = lane_shift_i<D>(int(b >> 32));
+    return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+
 // uniform base (SGPRs) + 32-bit byte offset (VGPR): lets the compiler use
 // the global_load/store "saddr + voffset" form instead of 64-bit lane addresses
 template <class T>
@@ -446,15 +470,103 @@ __device__ inline void store_partial(const AccT<S>& acc, double* out, double* ld
     }
 }
 
+// The same, plus the rn <= kMaxTileH partials rp[0], rp[rstride kNStat], ...
+// written by an earlier kernel: they are fetched by the whole workgroup at
+// once, summed in fixed segments of eight, and the segments added after the
+// waves in order.  rowbuf holds kMaxTileH * kNStat + 8 * kNStat doubles.
+template <class S>
+__device__ inline void store_partial_rows(const AccT<S>& acc, double* out, double* lds, const double* rp, int rn,
+                                          long long rstride, double* rowbuf)
+{
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthr = blockDim.x * blockDim.y;
+    for (int e = tid; e < rn * kNStat; e += nthr) {
+        const int j = e / kNStat, k = e - j * kNStat;
+        rowbuf[e] = rp[j * rstride * kNStat + k];
+    }
+    double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
+                        double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
+                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid)};
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) {
+            double o = __shfl_xor(v[k], off, 64);
+            v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kNStat; ++k) lds[wave * kNStat + k] = v[k];
+    }
+    __syncthreads();
+    double* seg = rowbuf + kMaxTileH * kNStat;     // [kNStat][8]
+    if (tid < 8 * kNStat) {
+        const int k = tid >> 3, g = tid & 7;
+        double s = k == kSMax ? -__builtin_huge_val() : 0.0;
+        for (int j = 8 * g; j < rn && j < 8 * g + 8; ++j) {
+            const double r = rowbuf[j * kNStat + k];
+            s = (k == kSMax) ? fmax(s, r) : s + r;
+        }
+        seg[tid] = s;
+    }
+    __syncthreads();
+    if (tid < kNStat) {
+        const int nw = nthr >> 6;
+        double s = lds[tid];
+        for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) s = (tid == kSMax) ? fmax(s, seg[tid * 8 + g]) : s + seg[tid * 8 + g];
+        out[tid] = s;
+    }
+}
+
+// Partial of a workgroup whose threads hold at most one node each: the
+// sums (FP32 for reduced storage, FP64 for FP64 storage) by a fixed xor
+// butterfly in each wave, the 0/1 counts by ballots, the waves combined in
+// FP64 in order.
+template <class S>
+__device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */)
+{
+    S v[8] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent};
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const S o = __shfl_xor(v[k], off, 64);
+            v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+    const double cnt[5] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
+                           double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
+                           double(__popcll(__ballot(acc.fluid != 0)))};
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
+    }
+    __syncthreads();
+    if (tid < kNStat) {
+        const int nw = (blockDim.x * blockDim.y) >> 6;
+        double s = lds[tid];
+        for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
+        out[tid] = s;
+    }
+}
+
 constexpr int kSmallDomainTiles = 32;
 
 __device__ inline void reduce_partials(const StepArgs& a, int parity, long long step, double* lds)
 {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthr = blockDim.x * blockDim.y;
-    // partials of the collision kernel, then (if it ran) of the median kernel
-    const double* part = a.partials + (long long)parity * 2 * a.ntiles * kNStat;
-    const int nsets = a.median_pass ? 2 : 1;
+    // one partial per tile (for D2Q9 it already holds the tile's collision rows)
+    const double* part = a.partials + (long long)parity * a.ntiles * kNStat;
+    const int nsets = 1;
     // domains with few tiles: one thread each, tiles summed in order
     for (int d = tid; d < a.ndomains; d += nthr) {
         const DomainDev& D = a.dom[d];

@@ -77,9 +77,9 @@ __device__ inline int tile_of_block(const StepArgs& a, int first)
     return xcd_spatial(int(blockIdx.x) - first, a.ntiles);
 }
 
-__device__ inline double* partial_slot(const StepArgs& a, int kernel, int tile)
+__device__ inline double* partial_slot(const StepArgs& a, int tile)
 {
-    return a.partials + (((long long)a.parity * 2 + kernel) * a.ntiles + tile) * kNStat;
+    return a.partials + ((long long)a.parity * a.ntiles + tile) * kNStat;
 }
 
 // trimming factor of one node (it depends on the node alone, Sec. 3.2/3.4)
@@ -169,8 +169,11 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
         reduce_block(a, red);
         return;
     }
-    const int tidx = tile_of_block(a, 1);
-    const Tile t = a.tiles[tidx];
+    // one row segment per workgroup, in row-major order: the grid streams
+    // through the domain a few rows at a time (DRAM pages and the rows that
+    // neighbours pull from stay few), one node per thread
+    const int ridx = int(blockIdx.x) - 1;
+    const Tile t = a.rows[ridx];
     const DomainDev& D = a.dom[t.domain];
     const int nx = D.nx, ny = D.ny;
     const long long plane = D.plane;
@@ -185,14 +188,10 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     const Cols<T, BC> cl(t.x0 + int(threadIdx.x), nx, t.x0 + int(threadIdx.x) < t.x1);
     AccT<A> acc;
     if (cl.ok) {
-        // loads of the next row are issued before the current row is processed
-        A gn[Q];
-        gather2d<BC>(src, plane, nx, ny, cl, t.y0, gn);
-        for (int y = t.y0; y < t.y1; ++y) {
+        {
+            const int y = t.y0;
             A g[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) g[i] = gn[i];
-            if (y + 1 < t.y1) gather2d<BC>(src, plane, nx, ny, cl, y + 1, gn);
+            gather2d<BC>(src, plane, nx, ny, cl, y, g);
             const long long row = (long long)y * nx;
             const unsigned node = unsigned(row) + unsigned(cl.x);
             const int cls = node_class<BC>(cl.x, y, nx, ny);
@@ -257,7 +256,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
             }
         }
     }
-    store_partial(acc, partial_slot(a, 0, tidx), red);
+    node_partial(acc, a.rowpart + (long long)ridx * kNStat, red);
 }
 
 // Median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the Delta S' plane
@@ -326,25 +325,54 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
             xp = x < nx - 1 ? x + 1 : x;
         }
         // rows y0-1 .. y1 are read; y1 <= ny, so one wrap keeps them in range
-        auto load_row = [&](int y, A (&r)[3]) {
+        auto row_of = [&](int y) -> long long {
             int yy;
             if constexpr (BC == kPeriodic)
                 yy = y < 0 ? y + ny : (y >= ny ? y - ny : y);
             else
                 yy = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
-            const long long rr = (long long)yy * nx;
+            return (long long)yy * nx;
+        };
+        auto load_row = [&](int y, A (&r)[3]) {
+            const long long rr = row_of(y);
             r[0] = Store<A>::ld(dsb + (rr + xm));
             r[1] = Store<A>::ld(dsb + (rr + x));
             r[2] = Store<A>::ld(dsb + (rr + xp));
         };
+        // Each lane loads its own column (one aligned load per row); the
+        // columns x -+ 1 come from the neighbouring lanes.  Only the first
+        // lane of a wave and the lane at the right end of a wave or of the
+        // tile load their outside neighbour themselves.
+        const int lane = int(threadIdx.x) & (kWave - 1);
+        const bool own_l = lane == 0;
+        const bool own_r = lane == kWave - 1 || x == t.x1 - 1;
+        auto load_own = [&](int y, A (&r)[3]) {
+            const long long rr = row_of(y);
+            r[1] = Store<A>::ld(dsb + (rr + x));
+            if (own_l) r[0] = Store<A>::ld(dsb + (rr + xm));
+            if (own_r) r[2] = Store<A>::ld(dsb + (rr + xp));
+        };
+        auto complete = [&](A (&r)[3]) {
+            // every active lane takes part in the shifts (no branch around them)
+            const A l = lane_shift<-1>(r[1]), rr = lane_shift<+1>(r[1]);
+            r[0] = own_l ? r[0] : l;
+            r[2] = own_r ? r[2] : rr;
+        };
         // w[k] holds row yb - 1 + k of the current chunk
         A w[kMedChunk + 2][3];
-        load_row(t.y0 - 1, w[0]);
-        load_row(t.y0, w[1]);
+#pragma unroll
+        for (int k = 0; k < kMedChunk + 2; ++k) w[k][0] = w[k][2] = A(0);
+        load_own(t.y0 - 1, w[0]);
+        load_own(t.y0, w[1]);
+        complete(w[0]);
+        complete(w[1]);
         for (int yb = t.y0; yb < t.y1; yb += kMedChunk) {
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k)
-                if (yb + k + 1 <= t.y1) load_row(yb + k + 1, w[k + 2]);
+                if (yb + k + 1 <= t.y1) load_own(yb + k + 1, w[k + 2]);
+#pragma unroll
+            for (int k = 0; k < kMedChunk; ++k)
+                if (yb + k + 1 <= t.y1) complete(w[k + 2]);
             unsigned hits = 0;
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k) {
@@ -397,7 +425,11 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
             }
         }
     }
-    store_partial(acc, partial_slot(a, 1, tidx), red);
+    // this tile's partial: the median pass's own terms, then the collision
+    // partials of the tile's rows (row table index row_first + y strips + strip)
+    const long long r0 = (long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads;
+    __shared__ double rowbuf[kMaxTileH * kNStat + 8 * kNStat];
+    store_partial_rows(acc, partial_slot(a, tidx), red, a.rowpart + r0 * kNStat, t.y1 - t.y0, D.strips, rowbuf);
 }
 
 // D1Q3: each workgroup computes Delta S' at kThreads consecutive sites and
@@ -491,7 +523,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
             to_global<double>(D.dS)[x] = double(S.dpost);
         }
     }
-    store_partial(acc, partial_slot(a, 0, tidx), red);
+    store_partial(acc, partial_slot(a, tidx), red);
 }
 
 // one instantiation per (quasiequilibrium, Delta S form, boundary) in use:
@@ -517,7 +549,7 @@ hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const Step
                                              hipStream_t s)
 {
     if (kernel == 0)
-        LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
+        LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.nrows + 1), dim3(kThreads), 0, s, a);
     else
         LBM_DISPATCH(k_median2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
