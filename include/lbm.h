@@ -93,7 +93,7 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT =
 #define LBM_RUN_RECORD 1u    /* keep per-node mask and Delta S' of every step */
 #define LBM_RUN_ENTROPY 2u   /* also accumulate sum S(f) (Sec. 4.3.1) */
 #define LBM_RUN_NO_GRAPH 4u  /* launch steps one by one (no hipGraph) */
-#define LBM_RUN_NO_TUNE 8u   /* skip the tile autotuner when tile_x == 0 */
+#define LBM_RUN_NO_TUNE 8u   /* accepted; the step kernels have a fixed shape */
 
 /* One simulation domain.  All domains of one context share lattice, qe,
  * ds_form and bc (they run in the same kernel); sizes, beta, limiter and
@@ -125,9 +125,9 @@ typedef struct {
     int32_t device;             /* HIP device ordinal */
     int32_t stats_every;        /* >0: lbm_step synchronises every k steps and
                                    returns LBM_EUNSTABLE on non-finite moments */
-    int32_t tile_x, tile_y;     /* D2Q9 tiles are 256 columns (one workgroup,
-                                   one node per thread): pass 0 (or 256 and 1) */
-    int32_t tile_h;             /* rows per D2Q9 tile (1..64); 0 = autotuned */
+    int32_t tile_x, tile_y;     /* D2Q9 workgroups take 256 columns of one row
+                                   (one node per thread): pass 0 (or 256 and 1) */
+    int32_t tile_h;             /* rows per D2Q9 median/reduction tile (1..64); 0 = 64 */
     uint32_t flags;             /* LBM_RUN_* */
     int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
     int32_t graph_chunk;        /* steps per captured graph (even), 0 = 64 */
@@ -158,8 +158,8 @@ LBM_API int lbm_workspace_bytes(const lbm_domain_desc* domains, int32_t n_domain
                         const lbm_run_desc* run, size_t* bytes);
 
 /* Create a context: validates the descriptors, allocates (or carves the
- * workspace into) population buffers, builds f(x, 0) (f_init, or f*(rho, u)),
- * and tunes the tile shape.  Errors: EINVAL, ENOMEM, EDEVICE.  On error
+ * workspace into) population buffers, builds f(x, 0) (f_init, or f*(rho, u))
+ * and the work tables.  Errors: EINVAL, ENOMEM, EDEVICE.  On error
  * *out is NULL and nothing is leaked. */
 LBM_API int lbm_create(const lbm_domain_desc* domains, int32_t n_domains,
                const lbm_run_desc* run, lbm_ctx** out);
@@ -194,14 +194,16 @@ LBM_API int lbm_limiter_mask(lbm_ctx* ctx, int32_t domain, uint8_t* mask, double
 LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples,
                     int64_t* n_written);
 
-/* Tile shape in use (after autotuning): columns, 1, rows (D1Q3: 254, 1, 1). */
+/* Tile shape of the median pass and of the stats reduction: columns, 1, rows
+ * (D1Q3: 254, 1, 1). */
 LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
 
 /* sync; profiling aid outside the method.  Advances the state by n_steps
  * (1..4096) like lbm_step, but launches every step eagerly (no graph) with
  * HIP events around each kernel on the context's stream, and writes the
  * average duration in milliseconds of the collision kernel to ms[0] and of
- * the median kernel to ms[1] (0 when no median pass runs).  ms is a
+ * the median kernel to ms[1] (0 when no median pass runs).  The stats of the
+ * last step stay readable afterwards.  ms is a
  * caller-owned host array of 2 doubles.  LBM_EINVAL for a bad count or a
  * NULL pointer. */
 LBM_API int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms);

@@ -24,7 +24,6 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t kAlign = 256;
-constexpr int kMinTileH = 4;              // smallest autotuned D2Q9 tile height
 constexpr int k1DWidth = kThreads - 2;    // output sites of one D1Q3 workgroup
 
 // D2Q9 tiles: kThreads consecutive columns
@@ -81,7 +80,6 @@ struct lbm_ctx {
     long long steps_done = 0, finalized_for = -1;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
-    std::vector<double> tune_log;   // (rows per tile, us per step) pairs
     std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
     std::vector<Tile> rows_host;
     std::vector<DomainDev> dom_host;
@@ -227,7 +225,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
             h.off_dsbuf = off;
             off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
         }
-        const int min_h = run->tile_h > 0 ? std::min(run->tile_h, kMinTileH) : kMinTileH;
+        const int min_h = run->tile_h > 0 ? run->tile_h : kMaxTileH;
         const int tiles = h.d.lattice == LBM_D2Q9 ? strips_of(h.d.nx) * ((h.d.ny + min_h - 1) / min_h)
                                                   : (h.d.nx + k1DWidth - 1) / k1DWidth;
         L.max_tiles += tiles;
@@ -239,7 +237,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     L.off_tiles = off;
     off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
     L.off_partials = off;
-    off = align_up(off + size_t(2) * L.max_tiles * kNStat * sizeof(double), kAlign);
+    off = align_up(off + size_t(4) * L.max_tiles * kNStat * sizeof(double), kAlign);
     L.off_rows = off;
     off = align_up(off + size_t(L.nrows) * sizeof(Tile), kAlign);
     L.off_rowpart = off;
@@ -355,6 +353,7 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.tiles = ctx->d_tiles();
     a.ntiles = ctx->ntiles;
     a.ndomains = int(ctx->dom.size());
+    a.median_pass = ctx->median_pass ? 1 : 0;
     a.rows = ctx->d_rows();
     a.nrows = ctx->lay.nrows;
     a.rowpart = ctx->d_rowpart();
@@ -379,7 +378,7 @@ int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
             e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
-    if (e == hipSuccess && ctx->lattice == LBM_D2Q9)
+    if (e == hipSuccess && ctx->lattice == LBM_D2Q9 && ctx->median_pass)
         e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], ctx->stream);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -406,47 +405,11 @@ void drop_graphs(lbm_ctx* ctx)
         }
 }
 
-// Time candidate tile heights on the live state (reads buffer 0, writes
-// buffer 1, which the first real step overwrites anyway).
+// The step kernels work on row segments of kThreads columns; D2Q9 tiles only
+// group rows for the reduction of the stats (and fix its summation order).
 int autotune(lbm_ctx* ctx, int fixed_th)
 {
-    int max_ny = 0;
-    for (const auto& h : ctx->dom) max_ny = std::max(max_ny, h.d.ny);
-    if (fixed_th) return set_tiles(ctx, fixed_th);
-    std::vector<int> ths;
-    for (int th : {4, 8, 16, 32, 64})
-        if (th <= std::max(kMinTileH, max_ny)) ths.push_back(th);
-    if (ths.size() == 1 || (ctx->flags & LBM_RUN_NO_TUNE))
-        return set_tiles(ctx, std::min(16, std::max(kMinTileH, max_ny)));
-    hipEvent_t e0, e1;
-    HIP_TRY(ctx, hipEventCreate(&e0));
-    HIP_TRY(ctx, hipEventCreate(&e1));
-    double best = 1e300;
-    int bth = ths[0];
-    for (int th : ths) {
-        int rc = set_tiles(ctx, th);
-        if (rc) return rc;
-        for (int w = 0; w < 2; ++w)
-            if ((rc = launch_one(ctx, 0))) return rc;
-        const int reps = 5;
-        HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
-        for (int r = 0; r < reps; ++r)
-            if ((rc = launch_one(ctx, 0))) return rc;
-        HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
-        HIP_TRY(ctx, hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
-        const double us = 1000.0 * ms / reps;
-        ctx->tune_log.push_back(th);
-        ctx->tune_log.push_back(us);
-        if (us < best) {
-            best = us;
-            bth = th;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return set_tiles(ctx, bth);
+    return set_tiles(ctx, fixed_th ? fixed_th : kMaxTileH);
 }
 
 int capture(lbm_ctx* ctx, int parity)
@@ -855,7 +818,7 @@ int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     ms[0] = t[0] / double(n_steps);
-    ms[1] = ctx->lattice == LBM_D2Q9 ? t[1] / double(n_steps) : 0.0;
+    ms[1] = (ctx->lattice == LBM_D2Q9 && ctx->median_pass) ? t[1] / double(n_steps) : 0.0;
     return LBM_OK;
 }
 

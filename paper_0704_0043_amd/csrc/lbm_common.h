@@ -76,14 +76,16 @@ struct Tile {
 struct StepArgs {
     const DomainDev* dom;
     const Tile* tiles;      // spatial order (domain, row chunk, column strip)
-    int ntiles;             // the second D2Q9 pass (and D1Q3) has one workgroup per tile
+    int ntiles;             // the D2Q9 median pass (and D1Q3) has one workgroup per tile
     int ndomains;
     int parity;             // read buf[parity], write buf[1 - parity]
     unsigned flags;
-    double* partials;       // [2 parities][ntiles][kNStat]: FP64 stats of each tile
+    double* partials;       // [2 parities][2 sets][ntiles][kNStat]: FP64 stats of each tile
+                            // (set 0: collision, set 1: median pass)
+    int median_pass;        // 1 if the median kernel runs after the collision kernel
     const Tile* rows;       // D2Q9 row segments in row-major order, one per collision workgroup
-    int nrows;              // the collision grid has nrows + 1 blocks; block 0 reduces
-    double* rowpart;        // [nrows][kNStat]: collision partials, summed by the second pass
+    int nrows;              // the D2Q9 collision grid has nrows blocks
+    double* rowpart;        // [nrows][kNStat]: collision partials of the last step
     long long* counter;     // [2] step index by parity
 };
 

@@ -564,9 +564,10 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
 {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthr = blockDim.x * blockDim.y;
-    // one partial per tile (for D2Q9 it already holds the tile's collision rows)
-    const double* part = a.partials + (long long)parity * a.ntiles * kNStat;
-    const int nsets = 1;
+    // set 0: collision partials (D2Q9: summed from the rows on demand); set 1:
+    // the median pass, when it ran
+    const double* part = a.partials + (long long)parity * 2 * a.ntiles * kNStat;
+    const int nsets = a.median_pass ? 2 : 1;
     // domains with few tiles: one thread each, tiles summed in order
     for (int d = tid; d < a.ndomains; d += nthr) {
         const DomainDev& D = a.dom[d];

@@ -1,25 +1,26 @@
 // Fused limited LBGK step kernels for gfx950.
 //
-// Compiled once per population storage type (LBM_ST = 0..3).  A time step of
-// every domain in the tile table is one launch of the collision kernel and,
-// when the median filter is on, one launch of the median kernel:
+// Compiled once per population storage type (LBM_ST = 0..3).  A D2Q9 time
+// step of every domain is one launch of the collision kernel and, when the
+// median filter is on, one launch of the median kernel:
 //
-//  collision: one thread per node, 256 consecutive columns x R rows per
-//    workgroup.  Free flight (pull form, read from buffer `parity`), moments,
-//    f*, over-relaxation, Delta S', the trimming factor (it depends on the
-//    node alone), and the store of the limited post-collision state into the
-//    other buffer.  With the median filter on, Delta S' also goes to a plane
-//    of its own.
+//  collision: one thread per node, one workgroup per row segment of 256
+//    columns, segments in row-major order, so the whole grid streams through
+//    a narrow band of rows at a time.  Free flight (pull form, read from
+//    buffer `parity`), moments, f*, over-relaxation, Delta S', the trimming
+//    factor (it depends on the node alone), and the store of the limited
+//    post-collision state into the other buffer.  With the median filter on,
+//    Delta S' also goes to a plane of its own.  Each workgroup leaves one
+//    partial of the reduction terms; the FP64 global sums are formed from
+//    these on demand, when the stats are read.
 //  median: the 3x3 median of that plane decides the filter; the few nodes
 //    whose factor drops below the trimming factor are collided again (the
 //    same arithmetic, bit-identical) from the untouched source buffer and
 //    overwritten.
 //
-// Both kernels are plain streaming passes with one node per lane, aligned
-// stores and no barrier in the node loop, the access pattern that sustains
-// the highest HBM bandwidth on this part.  Block 0 of the collision grid
-// reduces the previous step's per-tile FP64 partials into the domain stats
-// while the other blocks run.
+// The collision kernel is a plain streaming pass with aligned loads and
+// stores and no barrier before its epilogue, the access pattern that
+// sustains the highest HBM bandwidth on this part.
 #include <type_traits>
 
 #include "lbm_device.h"
@@ -77,9 +78,11 @@ __device__ inline int tile_of_block(const StepArgs& a, int first)
     return xcd_spatial(int(blockIdx.x) - first, a.ntiles);
 }
 
-__device__ inline double* partial_slot(const StepArgs& a, int tile)
+// per-tile FP64 partials: set 0 = collision rows (summed on demand; the D1Q3
+// kernel writes it directly), set 1 = median pass
+__device__ inline double* partial_slot(const StepArgs& a, int set, int tile)
 {
-    return a.partials + ((long long)a.parity * a.ntiles + tile) * kNStat;
+    return a.partials + (((long long)a.parity * 2 + set) * a.ntiles + tile) * kNStat;
 }
 
 // trimming factor of one node (it depends on the node alone, Sec. 3.2/3.4)
@@ -165,14 +168,10 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     using L = Lat<kD2Q9>;
     constexpr int Q = 9;
     __shared__ double red[4 * kNStat];
-    if (blockIdx.x == 0) {
-        reduce_block(a, red);
-        return;
-    }
     // one row segment per workgroup, in row-major order: the grid streams
     // through the domain a few rows at a time (DRAM pages and the rows that
     // neighbours pull from stay few), one node per thread
-    const int ridx = int(blockIdx.x) - 1;
+    const int ridx = int(blockIdx.x);
     const Tile t = a.rows[ridx];
     const DomainDev& D = a.dom[t.domain];
     const int nx = D.nx, ny = D.ny;
@@ -185,6 +184,8 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     const bool want_ent = a.flags & kFlagEntropy;
     const bool keep_ds = D.limiter & kLimMedian;
     const long long step = a.counter[a.parity];
+    // the index of the next step, read by the next launch (which reads buffer 1 - parity)
+    if (ridx == 0 && threadIdx.x == 0) a.counter[1 - a.parity] = step + 1;
     const Cols<T, BC> cl(t.x0 + int(threadIdx.x), nx, t.x0 + int(threadIdx.x) < t.x1);
     AccT<A> acc;
     if (cl.ok) {
@@ -425,11 +426,7 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
             }
         }
     }
-    // this tile's partial: the median pass's own terms, then the collision
-    // partials of the tile's rows (row table index row_first + y strips + strip)
-    const long long r0 = (long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads;
-    __shared__ double rowbuf[kMaxTileH * kNStat + 8 * kNStat];
-    store_partial_rows(acc, partial_slot(a, tidx), red, a.rowpart + r0 * kNStat, t.y1 - t.y0, D.strips, rowbuf);
+    store_partial(acc, partial_slot(a, 1, tidx), red);
 }
 
 // D1Q3: each workgroup computes Delta S' at kThreads consecutive sites and
@@ -523,7 +520,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
             to_global<double>(D.dS)[x] = double(S.dpost);
         }
     }
-    store_partial(acc, partial_slot(a, tidx), red);
+    store_partial(acc, partial_slot(a, 0, tidx), red);
 }
 
 // one instantiation per (quasiequilibrium, Delta S form, boundary) in use:
@@ -549,7 +546,7 @@ hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const Step
                                              hipStream_t s)
 {
     if (kernel == 0)
-        LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.nrows + 1), dim3(kThreads), 0, s, a);
+        LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.nrows), dim3(kThreads), 0, s, a);
     else
         LBM_DISPATCH(k_median2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
