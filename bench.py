@@ -151,6 +151,25 @@ def variants(torch, L, wl, stream, args):
         shear[name]["vs_f32"] = round(shear[name]["mlups"] / shear["f32"]["mlups"], 3)
     res["shear_8192"] = shear
 
+    # the headline step with the median filter working in every tile: delta
+    # below the Delta S' of most nodes (the headline's delta is above all of
+    # them, so there every median tile finds no candidate and skips)
+    print("[bench] variant 4096^2 with the median filter active", file=sys.stderr, flush=True)
+    act = {}
+    for dmed in (1e-9, 0.0):
+        dom = c2_domain(L, wl, 4096)
+        dom.delta_median = dmed
+        with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
+            ms = time_steps(torch, L, ctx, stream, steps, 16)
+            st = L.lbm_entropy_stats(ctx)
+            k1, k2 = L.lbm_kernel_times(ctx, 20)
+        sites = dom.nx * dom.ny
+        act[f"delta_median={dmed:g}"] = {
+            "mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
+            "collide_ms": round(k1, 5), "median_ms": round(k2, 5),
+            "filtered_fraction": round(st["n_filtered"] / sites, 4), "steps": steps}
+    res["median_active_4096"] = act
+
     print("[bench] variant cavity ensemble (256 domains)", file=sys.stderr, flush=True)
     batch = wl.cavity_batch(256)
     doms = []

@@ -19,14 +19,15 @@ enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2 };
 constexpr int kThreads = 256;      // workgroup size of the step kernels (= D2Q9 tile width)
 constexpr int kWave = 64;          // wavefront size (CDNA)
 constexpr int kMaxTileH = 64;      // rows per D2Q9 tile
-constexpr int kNStat = 13;         // FP64 values per tile partial
+constexpr int kNStat = 14;         // FP64 values per tile partial
 
 // partial / stats slot layout (FP64 each)
 enum {
     kSMass = 0,   // sum of rho - shift (the shift is added back on the host)
     kSJx, kSJy,
     kSDpre, kSDpost, kSMax, kSLim, kSEnt,
-    kSTrim, kSFilt, kSNonpos, kSNonfin, kSFluid
+    kSTrim, kSFilt, kSNonpos, kSNonfin, kSFluid,
+    kSAbove       // fluid nodes with Delta S' > delta_median (median filter candidates)
 };
 
 // Per-domain parameters, device visible.  Pointers are device pointers.

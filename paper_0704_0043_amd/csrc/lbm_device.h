@@ -255,13 +255,18 @@ struct SiteScalars {
     bool nonpos;
 };
 
-template <int LAT, int QE, int DS, class A>
-__device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, SiteState<LAT, A>& o,
-                                    SiteScalars& sc, bool want_pre)
+// Moments (eq. macro_dis) and the shifted equilibrium g*_i = f*_i - w_i shift
+// of a state g in shift form.  Also used on a limited state: the limiter keeps
+// rho and u, so its f* is the one it was limited toward.
+template <int LAT, int QE, class A>
+__device__ __forceinline__ void moments_equilibrium(const A (&g)[Lat<LAT>::Q], A shift, A& dr, A& jx, A& jy, A& rho,
+                                                    A& ux, A& uy, A (&gs)[Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q;
-    A dr = 0, jx = 0, jy = 0;
+    dr = 0;
+    jx = 0;
+    jy = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         dr += g[i];
@@ -270,9 +275,10 @@ __device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift,
         if (L::vy(i) > 0) jy += g[i];
         if (L::vy(i) < 0) jy -= g[i];
     }
-    A rho = shift + dr;              // eq. (macro_dis)
-    A inv = rcp(rho);
-    A ux = jx * inv, uy = jy * inv;
+    rho = shift + dr;
+    const A inv = rcp(rho);
+    ux = jx * inv;
+    uy = jy * inv;
     A E[Q];
     if constexpr (QE == kPoly) {
         // rho E_i = 3 v_i.j + rho (9 (v_i.u)^2 / 2 - 3 u^2 / 2): the linear
@@ -291,11 +297,22 @@ __device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift,
 #pragma unroll
         for (int i = 0; i < Q; ++i) E[i] = rho * E[i];
     }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gs[i] = A(L::w(i)) * (dr + E[i]);
+}
+
+template <int LAT, int QE, int DS, class A>
+__device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, SiteState<LAT, A>& o,
+                                    SiteScalars& sc, bool want_pre)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    A dr, jx, jy, rho, ux, uy;
+    moments_equilibrium<LAT, QE>(g, shift, dr, jx, jy, rho, ux, uy, o.gs);
     A fs[Q];
     bool fs_ok = true, pre_ok = true, post_ok = true;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        o.gs[i] = A(L::w(i)) * (dr + E[i]);
         fs[i] = A(L::w(i)) * shift + o.gs[i];
         o.d[i] = g[i] - o.gs[i];
         fs_ok &= fs[i] > A(0);
@@ -415,7 +432,7 @@ __device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const Dom
 template <class S>
 struct AccT {
     S mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
-    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0;
+    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0, above = 0;
 
     __device__ void moments(const SiteScalars& s)
     {
@@ -446,7 +463,7 @@ __device__ inline void store_partial(const AccT<S>& acc, double* out, double* ld
 {
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
-                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid)};
+                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -486,7 +503,7 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
     }
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
-                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid)};
+                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -538,16 +555,16 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
             v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
         }
     }
-    const double cnt[5] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
+    const double cnt[6] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
                            double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
-                           double(__popcll(__ballot(acc.fluid != 0)))};
+                           double(__popcll(__ballot(acc.fluid != 0))), double(__popcll(__ballot(acc.above != 0)))};
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
+        for (int k = 0; k < 6; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
     }
     __syncthreads();
     if (tid < kNStat) {

@@ -214,7 +214,10 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                 unsigned mask = 0;
                 const A phi = trim_phi(D, S.dpost, mask);
                 store_limited<T>(dst, plane, row, cl.own, S, phi, c);
-                if (keep_ds) Store<A>::st(dsb + node, S.dpost);
+                if (keep_ds) {
+                    Store<A>::st(dsb + node, S.dpost);
+                    if (S.dpost > A(D.delta_median)) acc.above = 1;
+                }
                 if (mask & kMaskTrim) {
                     ++acc.trim;
                     if (isfinite(S.dpost)) acc.lim += S.dpost - delta_s_scaled<kD2Q9, DS>(S, shift, c, phi);
@@ -268,6 +271,20 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
 // hits are handled after the chunk, one at a time.
 constexpr int kMedChunk = 16;
 
+// the filter's threshold and decision for a node with Delta S' = dc whose
+// stencil median is med (FLOOR or GATE reading of the tolerance delta)
+template <class A>
+__device__ __forceinline__ bool median_decide(const DomainDev& D, A dc, A med, A& thr)
+{
+    const A dmed = A(D.delta_median);
+    if (D.median_mode) {
+        thr = med;
+        return dc > dmed && dc > med;
+    }
+    thr = fmax(med, dmed);
+    return dc > thr;
+}
+
 // median threshold of a fluid node from its window (rows b, c, n = y-1, y, y+1;
 // columns l, m, r = x-1, x, x+1); returns whether the filter hits the node
 template <int BC, class A>
@@ -290,13 +307,7 @@ __device__ __forceinline__ bool median_hit(const DomainDev& D, int x, int y, int
         else
             med = median9(b[0], b[1], b[2], c[0], c[1], c[2], n[0], n[1], n[2]);
     }
-    const A dc = c[1], dmed = A(D.delta_median);
-    if (D.median_mode) {
-        thr = med;
-        return dc > dmed && dc > med;
-    }
-    thr = fmax(med, dmed);
-    return dc > thr;
+    return median_decide(D, c[1], med, thr);
 }
 
 template <class T, int QE, int DS, int BC>
@@ -311,10 +322,22 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
     AccT<A> acc;
     const int nx = D.nx, ny = D.ny;
     const int x = t.x0 + int(threadIdx.x);
-    if ((D.limiter & kLimMedian) && x < t.x1) {
+    // The filter's threshold is never below delta (FLOOR: max(median, delta);
+    // GATE: only nodes above delta), so a tile none of whose nodes has
+    // Delta S' > delta (the collision kernel counted them, in the same
+    // precision) has nothing to filter and skips the medians.
+    bool active = false;
+    if (D.limiter & kLimMedian) {
+        const long long r0 = (long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads;
+        const int rows = t.y1 - t.y0;
+        const bool cand = int(threadIdx.x) < rows &&
+                          a.rowpart[(r0 + (long long)threadIdx.x * D.strips) * kNStat + kSAbove] > 0.0;
+        active = __syncthreads_or(cand);
+    }
+    if (active && x < t.x1) {
         const long long plane = D.plane;
         const gptr<const A> dsb = to_global<A>(static_cast<const void*>(D.dsbuf));
-        const A shift = A(D.shift), c = A(D.c);
+        const A shift = A(D.shift);
         const bool record = a.flags & kFlagRecord;
         int xm, xp;
         if constexpr (BC == kPeriodic) {
@@ -333,12 +356,6 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
             else
                 yy = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
             return (long long)yy * nx;
-        };
-        auto load_row = [&](int y, A (&r)[3]) {
-            const long long rr = row_of(y);
-            r[0] = Store<A>::ld(dsb + (rr + xm));
-            r[1] = Store<A>::ld(dsb + (rr + x));
-            r[2] = Store<A>::ld(dsb + (rr + xp));
         };
         // Each lane loads its own column (one aligned load per row); the
         // columns x -+ 1 come from the neighbouring lanes.  Only the first
@@ -374,48 +391,57 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k)
                 if (yb + k + 1 <= t.y1) complete(w[k + 2]);
-            unsigned hits = 0;
+            // rows of the chunk in order; a filtered node is handled on the
+            // spot by the lanes that hit it (the row's other lanes idle)
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k) {
                 const int y = yb + k;
                 A thr;
                 if (y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid &&
-                    median_hit<BC>(D, x, y, nx, ny, w[k], w[k + 1], w[k + 2], thr))
-                    hits |= 1u << k;
-            }
-            // hit nodes: reload the window (cache-resident), take the same
-            // decision again, and collide again if the filter lowers phi
-            while (hits) {
-                const int k = __builtin_ctz(hits);
-                hits &= hits - 1;
-                const int y = yb + k;
-                A b[3], m[3], n[3], thr;
-                load_row(y - 1, b);
-                load_row(y, m);
-                load_row(y + 1, n);
-                median_hit<BC>(D, x, y, nx, ny, b, m, n, thr);
-                const A dc = m[1];
-                ++acc.filt;
-                unsigned tmask = 0;
-                const A pt = trim_phi(D, dc, tmask);
-                const A pm = sqrt_(thr * rcp(dc));
-                const long long rc = (long long)y * nx;
-                if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)kMaskMedian;
-                if (pm < pt) {
-                    // the filter lowers phi: collide this node again and overwrite
-                    const gptr<const T> src = to_global<T>(static_cast<const void*>(D.buf[a.parity]));
-                    const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
-                    const Cols<T, BC> cl(x, nx, true);
-                    A g[Q];
-                    gather2d<BC>(src, plane, nx, ny, cl, y, g);
-                    SiteState<kD2Q9, A> S;
-                    SiteScalars sc;
-                    collide_site<kD2Q9, QE, DS>(g, shift, c, S, sc, false);
-                    store_limited<T>(dst, plane, rc, cl.own, S, pm, c);
-                    if (isfinite(dc)) {
-                        // limiter entropy production: replace the trimming share
-                        const A before = pt < A(1) ? dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pt) : A(0);
-                        acc.lim += (dc - delta_s_scaled<kD2Q9, DS>(S, shift, c, pm)) - before;
+                    median_hit<BC>(D, x, y, nx, ny, w[k], w[k + 1], w[k + 2], thr)) {
+                    const A dc = w[k + 1][1];
+                    ++acc.filt;
+                    unsigned tmask = 0;
+                    const A pt = trim_phi(D, dc, tmask);
+                    const A pm = sqrt_(thr * rcp(dc));
+                    const long long rc = (long long)y * nx;
+                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)kMaskMedian;
+                    if (pm < pt) {
+                        // the filter lowers phi: rescale the limited state that
+                        // the collision kernel stored at this node toward its f*,
+                        // rebuilt from the state's own moments (the limiter kept
+                        // them): f* + (pm / pt)(f_stored - f*)
+                        const gptr<const T> lsrc = to_global<T>(static_cast<const void*>(D.buf[1 - a.parity]));
+                        const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
+                        const unsigned own = unsigned(sizeof(T)) * unsigned(x);
+                        A gl[Q], gs[Q];
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) gl[i] = Store<T>::ld(at_bytes(lsrc + (i * plane + rc), own));
+                        A dr, jx, jy, rho, ux, uy;
+                        moments_equilibrium<kD2Q9, QE>(gl, shift, dr, jx, jy, rho, ux, uy, gs);
+                        const A r = pm * rcp(pt);
+#pragma unroll
+                        for (int i = 0; i < Q; ++i)
+                            Store<T>::st(at_bytes(dst + (i * plane + rc), own), gs[i] + r * (gl[i] - gs[i]));
+                        if (isfinite(dc)) {
+                            // limiter entropy production: replace the trimming share
+                            A ds_pm, ds_pt;
+                            if constexpr (DS == kQuad) {
+                                ds_pm = pm * pm * dc;
+                                ds_pt = pt * pt * dc;
+                            } else {
+                                ds_pm = ds_pt = A(0);
+#pragma unroll
+                                for (int i = 0; i < Q; ++i) {
+                                    const A fs = A(Lat<kD2Q9>::w(i)) * shift + gs[i];
+                                    const A e = (gl[i] - gs[i]) * rcp(fs);
+                                    ds_pt += fs * hkern(e);
+                                    ds_pm += fs * hkern(r * e);
+                                }
+                            }
+                            const A before = pt < A(1) ? dc - ds_pt : A(0);
+                            acc.lim += (dc - ds_pm) - before;
+                        }
                     }
                 }
             }

@@ -236,6 +236,25 @@ def test_special_betas_and_zero_threshold(beta):
     assert_stats_close(pr)
 
 
+@pytest.mark.parametrize("tile", [16, None])
+def test_median_tiles_without_candidates(tile):
+    """Spikes only in a band of rows: median tiles elsewhere have no node
+    above delta and skip their medians; results must not change."""
+    o = orc()
+    rho, u = wl.random_flow(300, 140, seed=12, umax=0.05)
+    f0 = o.init_equilibrium(o.make_params(lattice=2, nx=300, ny=140, qe=0), rho, u)
+    spikes = wl.random_populations(9, 300, 140, seed=13, amp=0.0, spike_frac=0.3, spike_amp=0.4)
+    band = np.zeros((140, 300), dtype=bool)
+    band[70:100, 20:140] = True
+    f0 = np.where(band[None], spikes * (f0.sum(0) / spikes.sum(0))[None], f0)
+    pr = Pair(dom2d(nx=300, ny=140, qe=0, limiter=3, delta_trim=1e-2, delta_median=1e-6), f0, tile=tile)
+    assert pr.so["n_filtered"] > 0
+    assert_masks_equal(pr)
+    assert_ds_close(pr, 1e-12)
+    fields_close(pr)
+    assert_stats_close(pr)
+
+
 def test_equilibrium_state_is_left_alone():
     """All sites at f*: Delta S' is rounding noise (~1e-33) everywhere, so with a
     tiny positive threshold no site is limited (a zero threshold would decide
