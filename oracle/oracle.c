@@ -215,6 +215,10 @@ static int check_params(const orc_params* p)
     if (p->lattice == ORC_D1Q3 && p->ny != 1) return -1;
     if (!(p->beta >= 0.0 && p->beta <= 1.0)) return -1;
     if (!(p->delta_trim >= 0.0) || !(p->delta_median >= 0.0)) return -1;
+    if (p->limiter & (ORC_LIM_ENS_THRESHOLD | ORC_LIM_ENS_SMOOTH | ORC_LIM_ENS_RATIONAL | ORC_LIM_ENS_BUDGET)) {
+        if (!(p->delta_ens >= 0.0) || !(p->ens_c >= 0.0) || !(p->ens_k > 0.0)) return -1;
+        if ((p->limiter & ORC_LIM_ENS_RATIONAL) && !(p->ens_c > 0.0 && p->ens_k >= 0.5)) return -1;
+    }
     if (p->bc == ORC_BC_CAVITY) {
         if (p->lattice != ORC_D2Q9 || p->nx < 4 || p->ny < 4) return -1;
     } else if (p->bc == ORC_BC_TUBE) {
@@ -333,8 +337,34 @@ int orc_init_equilibrium(const orc_params* p, const double* rho,
  * post-collision state (eq. (LimGenF) with the trimming or median rule),
  * then free flight.  Cavity walls: bounce-back (reverse all populations, no
  * collision); lid nodes: set to f*(rho0, (u0, 0)) (Sec. 4.4.1). */
+static int cmp_descending(const void* a, const void* b)
+{
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x < y) - (x > y);
+}
+
+/* eq. (EntThresh) on the empirical distribution of the m finite values d
+ * (sorted here in descending order): the Delta S0 >= 0 with
+ * sum_x max(d_x - Delta S0, 0) = budget.  The left side is continuous and
+ * decreasing in Delta S0, linear between consecutive sorted values: with the
+ * k largest values above Delta S0 it reads S_k - k Delta S0. */
+static double budget_threshold(double* d, int m, double budget)
+{
+    if (m == 0) return 0.0;
+    qsort(d, (size_t)m, sizeof(double), cmp_descending);
+    if (!(budget > 0.0)) return d[0];
+    double sum = 0.0;
+    for (int k = 1; k <= m; ++k) {
+        sum += d[k - 1];
+        const double next = k < m ? d[k] : 0.0;
+        const double t = (sum - budget) / k;
+        if (t >= next) return t > 0.0 ? t : 0.0;
+    }
+    return 0.0;
+}
+
 int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
-             double* dS)
+             double* dS, double* dS_lim)
 {
     if (check_params(p)) return -1;
     const int q = orc_q(p->lattice), nx = p->nx, ny = p->ny, n = nx * ny;
@@ -353,6 +383,8 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
 
     orc_stats s;
     memset(&s, 0, sizeof(s));
+    if (dS_lim)
+        for (int k = 0; k < n; ++k) dS_lim[k] = 0.0;
     s.total_entropy = p->entropy ? 0.0 : NAN;
 
     /* pass 1: moments, collision, Delta S of every node */
@@ -404,6 +436,40 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 if (isfinite(e)) s.total_entropy += e;
             }
         }
+
+    /* ensemble quantities of the post-collision Delta S (Sec. 3.3, 3.4):
+     * E = mean over the fluid nodes (non-finite values left out of the sum),
+     * and the thresholds of the ensemble limiters */
+    const int ens = p->limiter & (ORC_LIM_ENS_THRESHOLD | ORC_LIM_ENS_SMOOTH | ORC_LIM_ENS_RATIONAL |
+                                  ORC_LIM_ENS_BUDGET);
+    double mean_ds = 0.0, t_thresh = 0.0, t_budget = 0.0;
+    {
+        double sum = 0.0;
+        int64_t nf = 0, nfin = 0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (node_type(p, x, y) != NODE_FLUID) continue;
+                nf++;
+                if (isfinite(dpost[y * nx + x])) {
+                    sum += dpost[y * nx + x];
+                    nfin++;
+                }
+            }
+        mean_ds = nf > 0 ? sum / (double)nf : 0.0;
+        t_thresh = p->ens_c * mean_ds > p->delta_ens ? p->ens_c * mean_ds : p->delta_ens;
+        if (p->limiter & ORC_LIM_ENS_BUDGET) {
+            double* vals = (double*)malloc(sizeof(double) * (nfin > 0 ? nfin : 1));
+            int mv = 0;
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    if (node_type(p, x, y) == NODE_FLUID && isfinite(dpost[y * nx + x]))
+                        vals[mv++] = dpost[y * nx + x];
+            const double b = p->ens_c * (1.0 - c * c) * sum;
+            const double s0 = budget_threshold(vals, mv, b);
+            free(vals);
+            t_budget = s0 > p->delta_ens ? s0 : p->delta_ens;
+        }
+    }
 
     /* pass 2: limiter on the post-collision state */
     double max_ds = 0.0;
@@ -457,19 +523,52 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                     }
                 }
             }
+            if (ens) {
+                double pe = 1.0;
+                if ((p->limiter & ORC_LIM_ENS_THRESHOLD) && d > t_thresh) {
+                    const double v = sqrt(t_thresh / d);    /* eq. (entrHom) */
+                    if (v < pe) pe = v;
+                }
+                if ((p->limiter & ORC_LIM_ENS_BUDGET) && d > t_budget) {
+                    const double v = sqrt(t_budget / d);
+                    if (v < pe) pe = v;
+                }
+                if ((p->limiter & ORC_LIM_ENS_SMOOTH) && mean_ds > 0.0 && d > 0.0) {
+                    /* eq. (smooth1) with a = delta / E^k */
+                    const double a = p->delta_ens / pow(mean_ds, p->ens_k);
+                    const double v = isinf(d) ? 0.0 : 1.0 / (1.0 + a * pow(d, p->ens_k));
+                    if (v < pe) pe = v;
+                }
+                if ((p->limiter & ORC_LIM_ENS_RATIONAL) && mean_ds > 0.0 && d > 0.0) {
+                    /* eq. (phiExamp), r = Delta S / (alpha E); only entropic
+                     * adjustments are kept (phi <= 1) */
+                    double v = 0.0;
+                    if (!isinf(d)) {
+                        const double r = d / (p->ens_c * mean_ds);
+                        v = (1.0 + pow(r, p->ens_k - 0.5)) / (1.0 + pow(r, p->ens_k));
+                    }
+                    if (v < pe) pe = v;
+                }
+                if (pe < 1.0) {
+                    m[site] |= ORC_MASK_ENSEMBLE;
+                    s.n_ensemble++;
+                    if (pe < phi) phi = pe;
+                }
+            }
             double fs[9], fl[9];
             for (int i = 0; i < q; ++i) {       /* eq. (LimGenF) */
                 fs[i] = fst[i * n + site];
                 fl[i] = fs[i] + phi * (fpost[i * n + site] - fs[i]);
                 o[i * n + site] = fl[i];
             }
-            if (phi < 1.0 && isfinite(d)) {
-                double after = orc_delta_s(q, p->ds_form, fl, fs);
-                s.limiter_production += d - after;
-            }
+            const double after = phi < 1.0 ? orc_delta_s(q, p->ds_form, fl, fs) : d;
+            if (phi < 1.0 && isfinite(d)) s.limiter_production += d - after;
+            if (dS_lim) dS_lim[site] = after;
         }
     s.max_dS = max_ds;
     s.lbgk_production = (1.0 - c * c) * s.sum_dS_pre;
+    s.mean_dS = mean_ds;
+    s.ens_threshold = (p->limiter & ORC_LIM_ENS_BUDGET) ? t_budget : t_thresh;
 
     /* pass 3: free flight */
     orc_stream(p, o, f);

@@ -39,14 +39,20 @@ extern "C" {
 enum { ORC_D1Q3 = 1, ORC_D2Q9 = 2 };
 enum { ORC_QE_POLY = 0, ORC_QE_ENTROPIC = 1 };
 enum { ORC_DS_EXACT = 0, ORC_DS_QUADRATIC = 1 };
-enum { ORC_LIM_TRIM = 1, ORC_LIM_MEDIAN = 2 };
+/* limiter bits: trimming (Sec. 3.2), median filter (Sec. 3.5), and the
+ * ensemble-dependent limiters, which use the mean E(Delta S) over the fluid
+ * nodes: threshold max(c E, delta) (Sec. 4.3.2), smooth phi = 1/(1 + a DS^k)
+ * with a = delta / E^k (eq. smooth1), the rational phi of eq. (phiExamp),
+ * and the entropy-budget threshold of eq. (EntThresh) */
+enum { ORC_LIM_TRIM = 1, ORC_LIM_MEDIAN = 2, ORC_LIM_ENS_THRESHOLD = 4, ORC_LIM_ENS_SMOOTH = 8,
+       ORC_LIM_ENS_RATIONAL = 16, ORC_LIM_ENS_BUDGET = 32 };
 enum { ORC_TRIM_HOMOTHETY = 0, ORC_TRIM_EHRENFEST = 1 };
 enum { ORC_MED_FLOOR = 0, ORC_MED_GATE = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_CAVITY = 1, ORC_BC_TUBE = 2 };
 
 /* mask bits written per node by orc_step */
 enum { ORC_MASK_TRIM = 1, ORC_MASK_MEDIAN = 2, ORC_MASK_NONPOS = 4,
-       ORC_MASK_NOTFLUID = 8 };
+       ORC_MASK_NOTFLUID = 8, ORC_MASK_ENSEMBLE = 16 };
 
 typedef struct {
     int32_t lattice, nx, ny;
@@ -55,6 +61,11 @@ typedef struct {
     double delta_trim, delta_median;
     double rho0, lid_ux;    /* cavity lid: f*(rho0, (lid_ux, 0)) */
     int32_t entropy;        /* nonzero: also sum S(f) over fluid nodes */
+    /* ensemble limiters: ens_c is c of the threshold c E, alpha of eq.
+     * (phiExamp), delta_0 of eq. (EntThresh); ens_k the exponent k of eqs.
+     * (smooth1) and (phiExamp); delta_ens the floor delta of the thresholds
+     * and the delta of a = delta / E^k */
+    double ens_c, ens_k, delta_ens;
 } orc_params;
 
 typedef struct {
@@ -62,6 +73,9 @@ typedef struct {
     double sum_dS_pre, sum_dS_post, max_dS;
     double lbgk_production, limiter_production, total_entropy;
     int64_t n_trimmed, n_filtered, n_nonpositive, n_nonfinite, n_fluid;
+    int64_t n_ensemble;     /* nodes an ensemble limiter moved (phi < 1) */
+    double mean_dS;         /* E(Delta S'): sum_dS_post / n_fluid */
+    double ens_threshold;   /* Delta S_t of the threshold / budget limiter */
 } orc_stats;
 
 int    orc_q(int32_t lattice);
@@ -79,9 +93,11 @@ double orc_h(double x);
 /* S(f) = -sum f_i ln(f_i / W_i) with the paper's W */
 double orc_entropy(int32_t lattice, const double* f);
 double orc_median(const double* v, int32_t n);
-/* one LBGK step + limiter + free flight; mask/dS may be NULL */
+/* one LBGK step + limiter + free flight; mask, dS (Delta S of the
+ * post-collision state) and dS_lim (Delta S of the limited state, the same
+ * form) may be NULL */
 int    orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
-                double* dS);
+                double* dS, double* dS_lim);
 /* free flight only: f = stream(o) (edge reflection at non-periodic edges) */
 int    orc_stream(const orc_params* p, const double* o, double* f);
 /* f = f*(rho, u) at every node; u is [dim][n] */

@@ -21,10 +21,11 @@ D1Q3, D2Q9 = 1, 2
 QE_POLY, QE_ENTROPIC = 0, 1
 DS_EXACT, DS_QUADRATIC = 0, 1
 LIM_TRIM, LIM_MEDIAN = 1, 2
+LIM_ENS_THRESHOLD, LIM_ENS_SMOOTH, LIM_ENS_RATIONAL, LIM_ENS_BUDGET = 4, 8, 16, 32
 TRIM_HOMOTHETY, TRIM_EHRENFEST = 0, 1
 MED_FLOOR, MED_GATE = 0, 1
 BC_PERIODIC, BC_CAVITY, BC_TUBE = 0, 1, 2
-MASK_TRIM, MASK_MEDIAN, MASK_NONPOS, MASK_NOTFLUID = 1, 2, 4, 8
+MASK_TRIM, MASK_MEDIAN, MASK_NONPOS, MASK_NOTFLUID, MASK_ENSEMBLE = 1, 2, 4, 8, 16
 
 
 class Params(ctypes.Structure):
@@ -36,6 +37,7 @@ class Params(ctypes.Structure):
         ("delta_trim", ctypes.c_double), ("delta_median", ctypes.c_double),
         ("rho0", ctypes.c_double), ("lid_ux", ctypes.c_double),
         ("entropy", ctypes.c_int32),
+        ("ens_c", ctypes.c_double), ("ens_k", ctypes.c_double), ("delta_ens", ctypes.c_double),
     ]
 
 
@@ -47,6 +49,7 @@ class Stats(ctypes.Structure):
         ("total_entropy", ctypes.c_double),
         ("n_trimmed", ctypes.c_int64), ("n_filtered", ctypes.c_int64),
         ("n_nonpositive", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+        ("n_ensemble", ctypes.c_int64), ("mean_dS", ctypes.c_double), ("ens_threshold", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -84,7 +87,7 @@ def lib():
         L.orc_median.argtypes = [dp, ctypes.c_int32]
         L.orc_median.restype = ctypes.c_double
         L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Stats),
-                               ctypes.POINTER(ctypes.c_uint8), dp]
+                               ctypes.POINTER(ctypes.c_uint8), dp, dp]
         L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
         L.orc_init_equilibrium.argtypes = [ctypes.POINTER(Params), dp, dp, dp]
         _lib = L
@@ -143,11 +146,12 @@ def median(v) -> float:
 
 def make_params(lattice=D2Q9, nx=8, ny=8, beta=0.9, qe=QE_POLY, ds_form=DS_EXACT, limiter=0,
                 trim_mode=TRIM_HOMOTHETY, median_mode=MED_FLOOR, bc=BC_PERIODIC, delta_trim=1e-3,
-                delta_median=1e-3, rho0=1.0, lid_ux=0.0, entropy=False) -> Params:
+                delta_median=1e-3, rho0=1.0, lid_ux=0.0, entropy=False, ens_c=0.0, ens_k=0.5,
+                delta_ens=0.0) -> Params:
     if lattice == D1Q3:
         ny = 1
     return Params(lattice, nx, ny, beta, qe, ds_form, limiter, trim_mode, median_mode, bc,
-                  delta_trim, delta_median, rho0, lid_ux, 1 if entropy else 0)
+                  delta_trim, delta_median, rho0, lid_ux, 1 if entropy else 0, ens_c, ens_k, delta_ens)
 
 
 def init_equilibrium(p: Params, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -162,25 +166,29 @@ def init_equilibrium(p: Params, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
     return f.reshape(q_of(p.lattice), p.ny, p.nx)
 
 
-def step(p: Params, f: np.ndarray, steps: int = 1, record: bool = False):
+def step(p: Params, f: np.ndarray, steps: int = 1, record: bool = False, record_lim: bool = False):
     """Advance f in place by `steps` steps; returns (stats of the last step,
-    mask, dS) with mask/dS of the last step when `record` is set."""
+    mask, dS) with mask/dS of the last step when `record` is set, and also
+    the Delta S of the limited states when `record_lim` is set."""
     assert f.dtype == np.float64 and f.flags.c_contiguous
     n = p.nx * p.ny
     st = Stats()
     mask = np.zeros(n, dtype=np.uint8) if record else None
     ds = np.zeros(n) if record else None
+    dsl = np.zeros(n) if record_lim else None
     L = lib()
     for k in range(steps):
         last = k == steps - 1
         mptr = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if (record and last) else None
         dptr = _dp(ds) if (record and last) else None
-        rc = L.orc_step(ctypes.byref(p), _dp(f), ctypes.byref(st), mptr, dptr)
+        lptr = _dp(dsl) if (record_lim and last) else None
+        rc = L.orc_step(ctypes.byref(p), _dp(f), ctypes.byref(st), mptr, dptr, lptr)
         if rc:
             raise ValueError(f"orc_step failed ({rc})")
-    if record:
-        return st, mask.reshape(p.ny, p.nx), ds.reshape(p.ny, p.nx)
-    return st, None, None
+    out = (st, mask.reshape(p.ny, p.nx) if record else None, ds.reshape(p.ny, p.nx) if record else None)
+    if record_lim:
+        out = out + (dsl.reshape(p.ny, p.nx),)
+    return out
 
 
 def stream(p: Params, o: np.ndarray) -> np.ndarray:
