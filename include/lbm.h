@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 #if defined(__GNUC__)
 #define LBM_API __attribute__((visibility("default")))
@@ -63,8 +63,21 @@ enum lbm_lattice { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
  * (entropiceq1d/maxwellian).  The D1Q3 entropic movers are taken with the
  * velocity they are labelled by: f*(v=+-1) = (rho/6)(+-3u - 1 + 2 sqrt(1+3u^2)). */
 enum lbm_qe { LBM_QE_POLYNOMIAL = 0, LBM_QE_ENTROPIC = 1 };
-/* limiter families, a bit mask: trimming (Sec. 3.2/3.4), median filter (Sec. 3.5) */
-enum lbm_limiter { LBM_LIM_NONE = 0, LBM_LIM_TRIM = 1, LBM_LIM_MEDIAN = 2 };
+/* limiter families, a bit mask: trimming (Sec. 3.2/3.4), median filter
+ * (Sec. 3.5), and the ensemble-dependent limiters, which use the mean
+ * E = E(Delta S') over the domain's fluid nodes of the same step:
+ *   ENS_THRESHOLD  Delta S_t = max(ens_c E, delta_ens), homothety above it
+ *                  (Sec. 4.3.2 with eq. entrHom)
+ *   ENS_SMOOTH     phi = 1 / (1 + a Delta S^ens_k), a = delta_ens / E^ens_k
+ *                  (eq. smooth1)
+ *   ENS_RATIONAL   phi = (1 + r^(k - 1/2)) / (1 + r^k), r = Delta S / (ens_c E),
+ *                  k = ens_k, kept <= 1 (eq. phiExamp)
+ *   ENS_BUDGET     Delta S_t = max(Delta S_0, delta_ens) with Delta S_0 solving
+ *                  sum max(Delta S - Delta S_0, 0) = ens_c [1 - (2 beta - 1)^2]
+ *                  sum Delta S on the domain's values (eq. EntThresh)
+ * When several are on, phi is the smallest of their factors. */
+enum lbm_limiter { LBM_LIM_NONE = 0, LBM_LIM_TRIM = 1, LBM_LIM_MEDIAN = 2, LBM_LIM_ENS_THRESHOLD = 4,
+                   LBM_LIM_ENS_SMOOTH = 8, LBM_LIM_ENS_RATIONAL = 16, LBM_LIM_ENS_BUDGET = 32 };
 /* trimming: homothety to Delta S_t = delta (eq. entrHom) or Ehrenfests' step
  * f -> f* (Sec. 3.2) at sites with Delta S > delta */
 enum lbm_trimmode { LBM_TRIM_HOMOTHETY = 0, LBM_TRIM_EHRENFEST = 1 };
@@ -88,6 +101,7 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT =
 #define LBM_MASK_MEDIAN 2u   /* median filter corrected the site */
 #define LBM_MASK_NONPOS 4u   /* a population or f* was <= 0 (Delta S = +inf) */
 #define LBM_MASK_NOTFLUID 8u /* wall or lid node: no collision, no limiter */
+#define LBM_MASK_ENSEMBLE 16u /* an ensemble-dependent limiter moved the node (phi < 1) */
 
 /* run flags */
 #define LBM_RUN_RECORD 1u    /* keep per-node mask and Delta S' of every step */
@@ -117,6 +131,10 @@ typedef struct {
     const double* u_init;       /* nullable host [dim][ny*nx]: initial velocity (default 0) */
     const double* f_init;       /* nullable host [Q][ny*nx]: initial state, overrides rho/u */
     int32_t probe_x, probe_y;   /* node whose (ux, uy) is recorded each step; -1 = none */
+    double ens_c;               /* ensemble limiters: c of the threshold c E, alpha of
+                                   the rational phi, delta_0 of the budget; >= 0 */
+    double ens_k;               /* exponent k of the smooth (> 0) and rational (>= 1/2) phi */
+    double delta_ens;           /* floor delta of the thresholds; delta of a = delta / E^k */
 } lbm_domain_desc;
 
 typedef struct {
@@ -149,6 +167,8 @@ typedef struct {
     double limiter_production;  /* sum (Delta S(f') - Delta S(f_limited)) (eq. LimEntLim) */
     double total_entropy;       /* sum S(f), S = -sum f ln(f/W); NaN unless LBM_RUN_ENTROPY */
     int64_t n_trimmed, n_filtered, n_nonpositive, n_nonfinite, n_fluid;
+    int64_t n_ensemble;         /* nodes an ensemble-dependent limiter moved */
+    double ens_threshold;       /* Delta S_t of ENS_BUDGET, else of ENS_THRESHOLD (0 if off) */
 } lbm_entropy_stats_t;
 
 typedef struct lbm_ctx lbm_ctx;

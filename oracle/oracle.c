@@ -568,7 +568,8 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
     s.max_dS = max_ds;
     s.lbgk_production = (1.0 - c * c) * s.sum_dS_pre;
     s.mean_dS = mean_ds;
-    s.ens_threshold = (p->limiter & ORC_LIM_ENS_BUDGET) ? t_budget : t_thresh;
+    s.ens_threshold = (p->limiter & ORC_LIM_ENS_BUDGET) ? t_budget
+                      : (p->limiter & ORC_LIM_ENS_THRESHOLD) ? t_thresh : 0.0;
 
     /* pass 3: free flight */
     orc_stream(p, o, f);

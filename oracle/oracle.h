@@ -75,7 +75,7 @@ typedef struct {
     int64_t n_trimmed, n_filtered, n_nonpositive, n_nonfinite, n_fluid;
     int64_t n_ensemble;     /* nodes an ensemble limiter moved (phi < 1) */
     double mean_dS;         /* E(Delta S'): sum_dS_post / n_fluid */
-    double ens_threshold;   /* Delta S_t of the threshold / budget limiter */
+    double ens_threshold;   /* Delta S_t of the budget limiter, else of the threshold limiter, else 0 */
 } orc_stats;
 
 int    orc_q(int32_t lattice);

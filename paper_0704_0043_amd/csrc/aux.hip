@@ -9,10 +9,10 @@ hipError_t launch_step2d_st0(int, int, int, const StepArgs&, int, hipStream_t);
 hipError_t launch_step2d_st1(int, int, int, const StepArgs&, int, hipStream_t);
 hipError_t launch_step2d_st2(int, int, int, const StepArgs&, int, hipStream_t);
 hipError_t launch_step2d_st3(int, int, int, const StepArgs&, int, hipStream_t);
-hipError_t launch_step1d_st0(int, int, int, const StepArgs&, hipStream_t);
-hipError_t launch_step1d_st1(int, int, int, const StepArgs&, hipStream_t);
-hipError_t launch_step1d_st2(int, int, int, const StepArgs&, hipStream_t);
-hipError_t launch_step1d_st3(int, int, int, const StepArgs&, hipStream_t);
+hipError_t launch_step1d_st0(int, int, int, const StepArgs&, int, hipStream_t);
+hipError_t launch_step1d_st1(int, int, int, const StepArgs&, int, hipStream_t);
+hipError_t launch_step1d_st2(int, int, int, const StepArgs&, int, hipStream_t);
+hipError_t launch_step1d_st3(int, int, int, const StepArgs&, int, hipStream_t);
 
 hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s)
 {
@@ -25,13 +25,13 @@ hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, hipStream_t s)
+hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s)
 {
     switch (storage) {
-    case kF64: return launch_step1d_st0(qe, ds, bc, a, s);
-    case kF32: return launch_step1d_st1(qe, ds, bc, a, s);
-    case kF16: return launch_step1d_st2(qe, ds, bc, a, s);
-    case kBF16: return launch_step1d_st3(qe, ds, bc, a, s);
+    case kF64: return launch_step1d_st0(qe, ds, bc, a, kernel, s);
+    case kF32: return launch_step1d_st1(qe, ds, bc, a, kernel, s);
+    case kF16: return launch_step1d_st2(qe, ds, bc, a, kernel, s);
+    case kBF16: return launch_step1d_st3(qe, ds, bc, a, kernel, s);
     }
     return hipErrorInvalidValue;
 }
@@ -54,6 +54,39 @@ __global__ void __launch_bounds__(kThreads) k_tile_rows(StepArgs a, int parity_d
     const Acc none;
     store_partial_rows(none, a.partials + ((long long)parity_done * 2 * a.ntiles + blockIdx.x) * kNStat, red,
                        a.rowpart + r0 * kNStat, t.y1 - t.y0, D.strips, rowbuf);
+}
+
+// E(Delta S') of this step and the thresholds of the ensemble limiters, per
+// domain (Sec. 3.3, 3.4): the collision partials (set 0; for D2Q9 summed from
+// the rows beforehand) are reduced exactly as the stats are, so E equals the
+// reported mean_dS bit for bit.
+__global__ void __launch_bounds__(kThreads) k_ens_prepare(StepArgs a, int parity)
+{
+    __shared__ double red[4 * kNStat];
+    StepArgs b = a;
+    b.median_pass = 0;
+    reduce_partials(b, parity, a.counter[parity], red);
+    __syncthreads();
+    for (int d = threadIdx.x; d < a.ndomains; d += blockDim.x) {
+        const DomainDev& D = a.dom[d];
+        if (!(D.limiter & kLimEns)) continue;
+        const double nf = D.stats[kSFluid];
+        const double mean = nf > 0.0 ? D.stats[kSDpost] / nf : 0.0;
+        D.ens[kEMean] = mean;
+        D.ens[kEThresh] = fmax(D.ens_c * mean, D.delta_ens);
+        D.ens[kESmoothA] = mean > 0.0 ? D.delta_ens / pow(mean, D.ens_k) : 0.0;
+    }
+}
+
+hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s)
+{
+    if (a.nrows > 0) {
+        hipLaunchKernelGGL(k_tile_rows, dim3(a.ntiles), dim3(kThreads), 0, s, a, a.parity);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_ens_prepare, dim3(1), dim3(kThreads), 0, s, a, a.parity);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s)

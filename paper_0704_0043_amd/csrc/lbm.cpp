@@ -48,7 +48,8 @@ struct DomainHost {
     long long plane = 0;
     size_t n = 0;
     size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0, off_dsbuf = 0;
-    bool dsbuf = false;
+    size_t off_ens = 0, off_phibuf = 0;
+    bool dsbuf = false, phibuf = false;
     double shift = 0;
     int tile_first = 0, tile_count = 0;
     int row_first = 0, row_count = 0;
@@ -77,6 +78,7 @@ struct lbm_ctx {
     int th = 16;            // rows per D2Q9 tile
     int ntiles = 0;
     bool median_pass = false;   // D2Q9 with the median filter in some domain
+    bool ens_pass = false;      // an ensemble-dependent limiter in some domain
     long long steps_done = 0, finalized_for = -1;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -132,7 +134,16 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
             return fail(nullptr, LBM_EINVAL, where + "lattice, qe, ds_form and bc must match across domains");
         if (d.qe != LBM_QE_POLYNOMIAL && d.qe != LBM_QE_ENTROPIC) return fail(nullptr, LBM_EINVAL, where + "bad qe");
         if (d.ds_form != LBM_DS_EXACT && d.ds_form != LBM_DS_QUADRATIC) return fail(nullptr, LBM_EINVAL, where + "bad ds_form");
-        if (d.limiter < 0 || d.limiter > 3) return fail(nullptr, LBM_EINVAL, where + "bad limiter mask");
+        if (d.limiter < 0 || d.limiter > 63) return fail(nullptr, LBM_EINVAL, where + "bad limiter mask");
+        if (d.limiter & kLimEns) {
+            if (!(d.ens_c >= 0.0) || !finite(d.ens_c) || !(d.ens_k > 0.0) || !finite(d.ens_k) ||
+                !(d.delta_ens >= 0.0) || !finite(d.delta_ens))
+                return fail(nullptr, LBM_EINVAL, where + "ensemble limiter needs finite ens_c >= 0, ens_k > 0, delta_ens >= 0");
+            if ((d.limiter & LBM_LIM_ENS_RATIONAL) && !(d.ens_c > 0.0 && d.ens_k >= 0.5))
+                return fail(nullptr, LBM_EINVAL, where + "rational limiter needs ens_c > 0 and ens_k >= 1/2");
+            if (d.limiter & LBM_LIM_ENS_BUDGET)
+                return fail(nullptr, LBM_EINVAL, where + "the budget threshold is not available on the GPU path");
+        }
         if (d.trim_mode != 0 && d.trim_mode != 1) return fail(nullptr, LBM_EINVAL, where + "bad trim_mode");
         if (d.median_mode != 0 && d.median_mode != 1) return fail(nullptr, LBM_EINVAL, where + "bad median_mode");
         if (d.nx < 1 || d.ny < 1) return fail(nullptr, LBM_EINVAL, where + "nx, ny must be >= 1");
@@ -220,11 +231,19 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         }
         h.off_stats = off;
         off = align_up(off + (kNStat + 1) * sizeof(double), kAlign);
-        h.dsbuf = h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN);
+        const bool ens = h.d.limiter & kLimEns;
+        h.dsbuf = (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN)) || ens;
         if (h.dsbuf) {
             h.off_dsbuf = off;
             off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
         }
+        h.phibuf = ens && h.d.lattice == LBM_D1Q3;
+        if (h.phibuf) {
+            h.off_phibuf = off;
+            off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
+        }
+        h.off_ens = off;
+        off = align_up(off + kNEns * sizeof(double), kAlign);
         const int min_h = run->tile_h > 0 ? run->tile_h : kMaxTileH;
         const int tiles = h.d.lattice == LBM_D2Q9 ? strips_of(h.d.nx) * ((h.d.ny + min_h - 1) / min_h)
                                                   : (h.d.nx + k1DWidth - 1) / k1DWidth;
@@ -326,6 +345,11 @@ int upload_domains(lbm_ctx* ctx)
         d.row_count = h.row_count;
         d.stats = reinterpret_cast<double*>(ctx->ws + h.off_stats);
         d.dsbuf = h.dsbuf ? ctx->ws + h.off_dsbuf : nullptr;
+        d.phibuf = h.phibuf ? ctx->ws + h.off_phibuf : nullptr;
+        d.ens = reinterpret_cast<double*>(ctx->ws + h.off_ens);
+        d.ens_c = h.d.ens_c;
+        d.ens_k = h.d.ens_k;
+        d.delta_ens = h.d.delta_ens;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_dom(), dd.data(), dd.size() * sizeof(DomainDev), hipMemcpyHostToDevice,
                                 ctx->stream));
@@ -353,7 +377,8 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.tiles = ctx->d_tiles();
     a.ntiles = ctx->ntiles;
     a.ndomains = int(ctx->dom.size());
-    a.median_pass = ctx->median_pass ? 1 : 0;
+    a.median_pass = (ctx->median_pass || ctx->ens_pass) ? 1 : 0;
+    a.ens_pass = ctx->ens_pass ? 1 : 0;
     a.rows = ctx->d_rows();
     a.nrows = ctx->lay.nrows;
     a.rowpart = ctx->d_rowpart();
@@ -375,11 +400,17 @@ int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
         if (ctx->lattice == LBM_D2Q9)
             e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 0, ctx->stream);
         else
-            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->stream);
+            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 0, ctx->stream);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
-    if (e == hipSuccess && ctx->lattice == LBM_D2Q9 && ctx->median_pass)
-        e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
+    // ensemble limiters: E(Delta S') of this step first (Sec. 3.3, 3.4)
+    if (e == hipSuccess && ctx->ens_pass) e = launch_ens_prepare(a, ctx->stream);
+    if (e == hipSuccess && (ctx->median_pass || ctx->ens_pass)) {
+        if (ctx->lattice == LBM_D2Q9)
+            e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
+        else
+            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
+    }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], ctx->stream);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return LBM_OK;
@@ -478,6 +509,15 @@ int read_stats(lbm_ctx* ctx, int32_t d, lbm_entropy_stats_t* out)
     s.n_filtered = (int64_t)raw[kSFilt];
     s.n_nonpositive = (int64_t)raw[kSNonpos];
     s.n_nonfinite = (int64_t)raw[kSNonfin];
+    s.n_ensemble = (int64_t)raw[kSEns];
+    if (h.d.limiter & (LBM_LIM_ENS_THRESHOLD | LBM_LIM_ENS_BUDGET)) {
+        double ev[kNEns] = {0, 0, 0, 0};
+        if (ctx->steps_done > 0) {
+            HIP_TRY(ctx, hipMemcpyAsync(ev, ctx->ws + h.off_ens, sizeof(ev), hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        s.ens_threshold = (h.d.limiter & LBM_LIM_ENS_BUDGET) ? ev[kEBudget] : ev[kEThresh];
+    }
     if (out) {
         const uint32_t keep = out->struct_size ? std::min<uint32_t>(out->struct_size, sizeof(s)) : sizeof(s);
         std::memcpy(out, &s, keep);
@@ -552,7 +592,10 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     ctx->probe_cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;
     ctx->graph_chunk = run->graph_chunk > 0 ? run->graph_chunk : 64;
     plan(ctx->dom, domains, n_domains, run, ctx->lay);
-    for (const auto& h : ctx->dom) ctx->median_pass = ctx->median_pass || h.dsbuf;
+    for (const auto& h : ctx->dom) {
+        ctx->median_pass = ctx->median_pass || (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN));
+        ctx->ens_pass = ctx->ens_pass || (h.d.limiter & kLimEns);
+    }
 
     auto bail = [&](int code) {
         release(ctx);
@@ -818,7 +861,7 @@ int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     ms[0] = t[0] / double(n_steps);
-    ms[1] = (ctx->lattice == LBM_D2Q9 && ctx->median_pass) ? t[1] / double(n_steps) : 0.0;
+    ms[1] = (ctx->median_pass || ctx->ens_pass) ? t[1] / double(n_steps) : 0.0;
     return LBM_OK;
 }
 

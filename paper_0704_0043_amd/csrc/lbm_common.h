@@ -10,16 +10,17 @@ enum { kD1Q3 = 1, kD2Q9 = 2 };
 enum { kPoly = 0, kEntropic = 1 };
 enum { kExact = 0, kQuad = 1 };
 enum { kPeriodic = 0, kCavity = 1, kTube = 2 };
-enum { kLimTrim = 1, kLimMedian = 2 };
+enum { kLimTrim = 1, kLimMedian = 2, kLimEnsThresh = 4, kLimEnsSmooth = 8, kLimEnsRational = 16,
+       kLimEnsBudget = 32, kLimEns = 4 | 8 | 16 | 32 };
 enum { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
-enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8 };
+enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8, kMaskEns = 16 };
 enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2 };
 
 constexpr int kThreads = 256;      // workgroup size of the step kernels (= D2Q9 tile width)
 constexpr int kWave = 64;          // wavefront size (CDNA)
 constexpr int kMaxTileH = 64;      // rows per D2Q9 tile
-constexpr int kNStat = 14;         // FP64 values per tile partial
+constexpr int kNStat = 15;         // FP64 values per tile partial
 
 // partial / stats slot layout (FP64 each)
 enum {
@@ -27,8 +28,12 @@ enum {
     kSJx, kSJy,
     kSDpre, kSDpost, kSMax, kSLim, kSEnt,
     kSTrim, kSFilt, kSNonpos, kSNonfin, kSFluid,
-    kSAbove       // fluid nodes with Delta S' > delta_median (median filter candidates)
+    kSAbove,      // fluid nodes with Delta S' > delta_median (median filter candidates)
+    kSEns         // nodes an ensemble-dependent limiter moved
 };
+
+// per-domain ensemble values of the current step (device array of kNEns doubles)
+enum { kEMean = 0, kEThresh, kESmoothA, kEBudget, kNEns };
 
 // Per-domain parameters, device visible.  Pointers are device pointers.
 struct DomainDev {
@@ -45,6 +50,9 @@ struct DomainDev {
     unsigned char* mask;    // [ny*nx] when recording
     double* dS;             // [ny*nx] when recording
     int tile_first, tile_count;   // this domain's range in the tile table
+    double ens_c, ens_k, delta_ens;   // ensemble limiter parameters
+    double* ens;                  // [kNEns]: E(Delta S') and the thresholds of this step
+    void* phibuf;                 // D1Q3 with ensemble limiters: phi applied by the first pass
     int strips;                   // D2Q9: column strips of kThreads columns
     int row_first, row_count;     // D2Q9: this domain's range in the row table
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
@@ -83,7 +91,8 @@ struct StepArgs {
     unsigned flags;
     double* partials;       // [2 parities][2 sets][ntiles][kNStat]: FP64 stats of each tile
                             // (set 0: collision, set 1: median pass)
-    int median_pass;        // 1 if the median kernel runs after the collision kernel
+    int median_pass;        // 1 if a second pass (median and/or ensemble limiters) writes set 1
+    int ens_pass;           // 1 if some domain has an ensemble-dependent limiter
     const Tile* rows;       // D2Q9 row segments in row-major order, one per collision workgroup
     int nrows;              // the D2Q9 collision grid has nrows blocks
     double* rowpart;        // [nrows][kNStat]: collision partials of the last step
@@ -93,7 +102,10 @@ struct StepArgs {
 // Launchers (one per storage type / lattice), defined in the .hip files.
 // kernel 0: collision kernel; kernel 1: median filter and tile reduction (after kernel 0)
 hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
-hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, hipStream_t s);
+// kernel 0: D1Q3 step; kernel 1: D1Q3 ensemble pass
+hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
+// E(Delta S') and ensemble thresholds of the step just run (before the second pass)
+hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);
 hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u, double* f, int nx, int ny,
                          hipStream_t s);

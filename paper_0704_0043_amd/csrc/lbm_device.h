@@ -141,6 +141,8 @@ struct Store<__bf16> {
 __device__ inline double rcp(double x) { return 1.0 / x; }
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double sqrt_(double x) { return sqrt(x); }
+__device__ inline double pow_(double x, double y) { return pow(x, y); }
+__device__ inline float pow_(float x, float y) { return powf(x, y); }
 __device__ inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double log1p_(double x) { return log1p(x); }
 __device__ inline float log1p_(float x) { return log1pf(x); }
@@ -432,7 +434,7 @@ __device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const Dom
 template <class S>
 struct AccT {
     S mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
-    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0, above = 0;
+    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0, above = 0, ens = 0;
 
     __device__ void moments(const SiteScalars& s)
     {
@@ -463,7 +465,8 @@ __device__ inline void store_partial(const AccT<S>& acc, double* out, double* ld
 {
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
-                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above)};
+                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above),
+                        double(acc.ens)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -503,7 +506,8 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
     }
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
-                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above)};
+                        double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above),
+                        double(acc.ens)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -555,16 +559,17 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
             v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
         }
     }
-    const double cnt[6] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
+    const double cnt[7] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
                            double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
-                           double(__popcll(__ballot(acc.fluid != 0))), double(__popcll(__ballot(acc.above != 0)))};
+                           double(__popcll(__ballot(acc.fluid != 0))), double(__popcll(__ballot(acc.above != 0))),
+                           double(__popcll(__ballot(acc.ens != 0)))};
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
+        for (int k = 0; k < 7; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
     }
     __syncthreads();
     if (tid < kNStat) {
@@ -573,6 +578,35 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
         for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
         out[tid] = s;
     }
+}
+
+// Factor of the ensemble-dependent limiters for a node with Delta S' = d,
+// from this step's E(Delta S') and thresholds (ens[kNEns]); 1 when none moves
+// the node.  Threshold and budget: homothety to Delta S_t above it (eq.
+// entrHom); smooth: eq. (smooth1) with a = delta / E^k; rational: eq.
+// (phiExamp) with r = d / (alpha E), kept <= 1 (only entropic moves).
+// +inf (a non-positive population) gives 0; NaN gives 1.
+template <class A>
+__device__ __forceinline__ A ens_phi(const DomainDev& D, const double* ens, A d)
+{
+    A pe = A(1);
+    const int lim = D.limiter;
+    if ((lim & kLimEnsThresh) && d > A(ens[kEThresh])) pe = fmin(pe, sqrt_(A(ens[kEThresh]) * rcp(d)));
+    if ((lim & kLimEnsBudget) && d > A(ens[kEBudget])) pe = fmin(pe, sqrt_(A(ens[kEBudget]) * rcp(d)));
+    const double mean = ens[kEMean];
+    if ((lim & kLimEnsSmooth) && mean > 0.0 && d > A(0)) {
+        const A v = isinf(d) ? A(0) : A(1) / (A(1) + A(ens[kESmoothA]) * pow_(d, A(D.ens_k)));
+        pe = fmin(pe, v);
+    }
+    if ((lim & kLimEnsRational) && mean > 0.0 && d > A(0)) {
+        A v = A(0);
+        if (!isinf(d)) {
+            const A r = d / A(D.ens_c * mean);
+            v = (A(1) + pow_(r, A(D.ens_k - 0.5))) / (A(1) + pow_(r, A(D.ens_k)));
+        }
+        pe = fmin(pe, v);
+    }
+    return pe;
 }
 
 constexpr int kSmallDomainTiles = 32;

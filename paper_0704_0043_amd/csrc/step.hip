@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     const A shift = A(D.shift), c = A(D.c);
     const bool record = a.flags & kFlagRecord;
     const bool want_ent = a.flags & kFlagEntropy;
-    const bool keep_ds = D.limiter & kLimMedian;
+    const bool keep_ds = D.limiter & (kLimMedian | kLimEns);
     const long long step = a.counter[a.parity];
     // the index of the next step, read by the next launch (which reads buffer 1 - parity)
     if (ridx == 0 && threadIdx.x == 0) a.counter[1 - a.parity] = step + 1;
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                 store_limited<T>(dst, plane, row, cl.own, S, phi, c);
                 if (keep_ds) {
                     Store<A>::st(dsb + node, S.dpost);
-                    if (S.dpost > A(D.delta_median)) acc.above = 1;
+                    if ((D.limiter & kLimMedian) && S.dpost > A(D.delta_median)) acc.above = 1;
                 }
                 if (mask & kMaskTrim) {
                     ++acc.trim;
@@ -310,8 +310,8 @@ __device__ __forceinline__ bool median_hit(const DomainDev& D, int x, int y, int
     return median_decide(D, c[1], med, thr);
 }
 
-template <class T, int QE, int DS, int BC>
-__global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
+template <class T, int QE, int DS, int BC, bool ENS>
+__device__ __forceinline__ void second_pass2d(const StepArgs& a)
 {
     using A = typename Store<T>::A;
     constexpr int Q = 9;
@@ -326,12 +326,33 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
     // GATE: only nodes above delta), so a tile none of whose nodes has
     // Delta S' > delta (the collision kernel counted them, in the same
     // precision) has nothing to filter and skips the medians.
+    // The ensemble limiters use this step's E(Delta S') and thresholds;
+    // threshold-type ones skip tiles whose largest Delta S' is at or below
+    // the threshold (and that hold no infinite value), the smooth ones move
+    // every node with Delta S' > 0.
     bool active = false;
-    if (D.limiter & kLimMedian) {
+    double ensv[kNEns] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (ENS) {
+        if (D.limiter & kLimEns) {
+#pragma unroll
+            for (int k = 0; k < kNEns; ++k) ensv[k] = D.ens[k];
+        }
+    }
+    if (D.limiter & (kLimMedian | kLimEns)) {
         const long long r0 = (long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads;
         const int rows = t.y1 - t.y0;
-        const bool cand = int(threadIdx.x) < rows &&
-                          a.rowpart[(r0 + (long long)threadIdx.x * D.strips) * kNStat + kSAbove] > 0.0;
+        bool cand = false;
+        if (int(threadIdx.x) < rows) {
+            const double* rp = a.rowpart + (r0 + (long long)threadIdx.x * D.strips) * kNStat;
+            const A mx = A(rp[kSMax]);
+            const bool inf = rp[kSNonpos] > 0.0;
+            if (D.limiter & kLimMedian) cand = cand || rp[kSAbove] > 0.0;
+            if constexpr (ENS) {
+                if (D.limiter & (kLimEnsSmooth | kLimEnsRational)) cand = cand || rp[kSFluid] > 0.0;
+                if (D.limiter & kLimEnsThresh) cand = cand || inf || mx > A(ensv[kEThresh]);
+                if (D.limiter & kLimEnsBudget) cand = cand || inf || mx > A(ensv[kEBudget]);
+            }
+        }
         active = __syncthreads_or(cand);
     }
     if (active && x < t.x1) {
@@ -391,21 +412,40 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k)
                 if (yb + k + 1 <= t.y1) complete(w[k + 2]);
-            // rows of the chunk in order; a filtered node is handled on the
-            // spot by the lanes that hit it (the row's other lanes idle)
+            // rows of the chunk in order; a node the median filter or an
+            // ensemble limiter moves is handled on the spot by its lane (the
+            // row's other lanes idle)
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k) {
                 const int y = yb + k;
-                A thr;
-                if (y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid &&
+                const A dc = w[k + 1][1];
+                A pm = A(1), thr;
+                bool med = false;
+                if ((D.limiter & kLimMedian) && y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid &&
                     median_hit<BC>(D, x, y, nx, ny, w[k], w[k + 1], w[k + 2], thr)) {
-                    const A dc = w[k + 1][1];
-                    ++acc.filt;
+                    med = true;
+                    pm = sqrt_(thr * rcp(dc));
+                }
+                A pe = A(1);
+                if constexpr (ENS) {
+                    if ((D.limiter & kLimEns) && y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid)
+                        pe = ens_phi(D, ensv, dc);
+                }
+                if (med || pe < A(1)) {
+                    unsigned bits = 0;
+                    if (med) {
+                        ++acc.filt;
+                        bits |= kMaskMedian;
+                    }
+                    if (pe < A(1)) {
+                        ++acc.ens;
+                        bits |= kMaskEns;
+                        pm = fmin(pm, pe);
+                    }
                     unsigned tmask = 0;
                     const A pt = trim_phi(D, dc, tmask);
-                    const A pm = sqrt_(thr * rcp(dc));
                     const long long rc = (long long)y * nx;
-                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)kMaskMedian;
+                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)bits;
                     if (pm < pt) {
                         // the filter lowers phi: rescale the limited state that
                         // the collision kernel stored at this node toward its f*,
@@ -453,6 +493,20 @@ __global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
         }
     }
     store_partial(acc, partial_slot(a, 1, tidx), red);
+}
+
+// the second D2Q9 pass without and with ensemble-dependent limiters (the
+// latter needs more registers)
+template <class T, int QE, int DS, int BC>
+__global__ void __launch_bounds__(kThreads) k_median2d(StepArgs a)
+{
+    second_pass2d<T, QE, DS, BC, false>(a);
+}
+
+template <class T, int QE, int DS, int BC>
+__global__ void __launch_bounds__(kThreads) k_median_ens2d(StepArgs a)
+{
+    second_pass2d<T, QE, DS, BC, true>(a);
 }
 
 // D1Q3: each workgroup computes Delta S' at kThreads consecutive sites and
@@ -545,8 +599,76 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
             to_global<unsigned char>(D.mask)[x] = (unsigned char)mask;
             to_global<double>(D.dS)[x] = double(S.dpost);
         }
+        if (D.limiter & kLimEns) {
+            // for the ensemble pass: Delta S' and the factor applied here
+            Store<A>::st(to_global<A>(D.dsbuf) + x, S.dpost);
+            Store<A>::st(to_global<A>(D.phibuf) + x, phi);
+        }
     }
     store_partial(acc, partial_slot(a, 0, tidx), red);
+}
+
+// D1Q3 ensemble pass (after the step kernel and the E(Delta S') reduction):
+// a site whose ensemble factor is below the factor the step kernel applied is
+// moved further toward its f*, rebuilt from the stored state's moments:
+// f* + (phi_ens / phi_applied)(f_stored - f*).
+template <class T, int QE, int DS, int BC>
+__global__ void __launch_bounds__(kThreads) k_ens1d(StepArgs a)
+{
+    using A = typename Store<T>::A;
+    constexpr int LAT = kD1Q3;
+    constexpr int Q = Lat<LAT>::Q;
+    __shared__ double red[4 * kNStat];
+    const int tidx = int(blockIdx.x);
+    const Tile t = a.tiles[tidx];
+    const DomainDev& D = a.dom[t.domain];
+    const int x = t.x0 + int(threadIdx.x);
+    AccT<A> acc;
+    if ((D.limiter & kLimEns) && x < t.x1) {
+        double ensv[kNEns];
+#pragma unroll
+        for (int k = 0; k < kNEns; ++k) ensv[k] = D.ens[k];
+        const A d = Store<A>::ld(to_global<A>(static_cast<const void*>(D.dsbuf)) + x);
+        const A pa = Store<A>::ld(to_global<A>(static_cast<const void*>(D.phibuf)) + x);
+        const A pe = ens_phi(D, ensv, d);
+        if (pe < A(1)) {
+            ++acc.ens;
+            if (a.flags & kFlagRecord) to_global<unsigned char>(D.mask)[x] |= (unsigned char)kMaskEns;
+            if (pe < pa) {
+                const long long plane = D.plane;
+                const A shift = A(D.shift);
+                const gptr<const T> lsrc = to_global<T>(static_cast<const void*>(D.buf[1 - a.parity]));
+                const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
+                A gl[Q], gs[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) gl[i] = Store<T>::ld(lsrc + (i * plane + x));
+                A dr, jx, jy, rho, ux, uy;
+                moments_equilibrium<LAT, QE>(gl, shift, dr, jx, jy, rho, ux, uy, gs);
+                const A r = pe * rcp(pa);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) Store<T>::st(dst + (i * plane + x), gs[i] + r * (gl[i] - gs[i]));
+                if (isfinite(d)) {
+                    A ds_pe, ds_pa;
+                    if constexpr (DS == kQuad) {
+                        ds_pe = pe * pe * d;
+                        ds_pa = pa * pa * d;
+                    } else {
+                        ds_pe = ds_pa = A(0);
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) {
+                            const A fs = A(Lat<LAT>::w(i)) * shift + gs[i];
+                            const A e = (gl[i] - gs[i]) * rcp(fs);
+                            ds_pa += fs * hkern(e);
+                            ds_pe += fs * hkern(r * e);
+                        }
+                    }
+                    // the step kernel counted d - Delta S(phi_applied)
+                    acc.lim += ds_pa - ds_pe;
+                }
+            }
+        }
+    }
+    store_partial(acc, partial_slot(a, 1, tidx), red);
 }
 
 // one instantiation per (quasiequilibrium, Delta S form, boundary) in use:
@@ -573,14 +695,20 @@ hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const Step
 {
     if (kernel == 0)
         LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.nrows), dim3(kThreads), 0, s, a);
+    else if (a.ens_pass)
+        LBM_DISPATCH(k_median_ens2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     else
         LBM_DISPATCH(k_median2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t LBM_CAT(launch_step1d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, hipStream_t s)
+hipError_t LBM_CAT(launch_step1d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, int kernel,
+                                             hipStream_t s)
 {
-    LBM_DISPATCH(k_step1d, 0, 2, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
+    if (kernel == 0)
+        LBM_DISPATCH(k_step1d, 0, 2, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
+    else
+        LBM_DISPATCH(k_ens1d, 0, 2, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
