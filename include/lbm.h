@@ -74,7 +74,12 @@ enum lbm_qe { LBM_QE_POLYNOMIAL = 0, LBM_QE_ENTROPIC = 1 };
  *                  k = ens_k, kept <= 1 (eq. phiExamp)
  *   ENS_BUDGET     Delta S_t = max(Delta S_0, delta_ens) with Delta S_0 solving
  *                  sum max(Delta S - Delta S_0, 0) = ens_c [1 - (2 beta - 1)^2]
- *                  sum Delta S on the domain's values (eq. EntThresh)
+ *                  sum Delta S on the domain's values (eq. EntThresh), found by
+ *                  a radix selection over the values' bit patterns whose
+ *                  bucket sums are exact integers: the threshold does not
+ *                  depend on the order of the additions (run to run equal).
+ *                  No budget (ens_c = 0) puts it at the largest value; a
+ *                  budget beyond sum Delta S puts it at 0
  * When several are on, phi is the smallest of their factors. */
 enum lbm_limiter { LBM_LIM_NONE = 0, LBM_LIM_TRIM = 1, LBM_LIM_MEDIAN = 2, LBM_LIM_ENS_THRESHOLD = 4,
                    LBM_LIM_ENS_SMOOTH = 8, LBM_LIM_ENS_RATIONAL = 16, LBM_LIM_ENS_BUDGET = 32 };
@@ -222,7 +227,9 @@ LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y
  * (1..4096) like lbm_step, but launches every step eagerly (no graph) with
  * HIP events around each kernel on the context's stream, and writes the
  * average duration in milliseconds of the collision kernel to ms[0] and of
- * the median kernel to ms[1] (0 when no median pass runs).  The stats of the
+ * the rest of the step to ms[1]: the ensemble reductions and selection (when
+ * an ensemble-dependent limiter is on) and the second pass (median filter,
+ * ensemble factors); 0 when no second pass runs.  The stats of the
  * last step stay readable afterwards.  ms is a
  * caller-owned host array of 2 doubles.  LBM_EINVAL for a bad count or a
  * NULL pointer. */

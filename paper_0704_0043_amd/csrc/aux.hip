@@ -75,7 +75,254 @@ __global__ void __launch_bounds__(kThreads) k_ens_prepare(StepArgs a, int parity
         D.ens[kEMean] = mean;
         D.ens[kEThresh] = fmax(D.ens_c * mean, D.delta_ens);
         D.ens[kESmoothA] = mean > 0.0 ? D.delta_ens / pow(mean, D.ens_k) : 0.0;
+        if (D.limiter & kLimEnsBudget) {
+            // eq. (EntThresh): the limiter may produce delta_0 times the
+            // entropy production of the LBGK step, [1 - (2 beta - 1)^2] sum Delta S
+            BudgetState& b = *D.bstate;
+            const double budget = D.ens_c * (1.0 - D.c * D.c) * D.stats[kSDpost];
+            b.prefix = 0;
+            b.budget = budget;
+            b.s_above = 0.0;
+            b.c_above = 0.0;
+            b.level = 0;
+            b.done = budget > 0.0 ? 0 : 1;
+            // no budget: the threshold sits at the largest value, nothing moves
+            D.ens[kEBudget] = fmax(budget > 0.0 ? 0.0 : D.stats[kSMax], D.delta_ens);
+        }
     }
+}
+
+// Keys of the budget selection: the bit pattern of a non-negative finite
+// value (0 for values <= 0), ordered as the values are.
+template <class A>
+struct BKey;
+template <>
+struct BKey<double> {
+    using U = unsigned long long;
+    static constexpr bool dbl = true;
+    static constexpr int mbits = 52, bias = 1075;
+    __device__ static U key(double d) { return d > 0.0 ? U(__double_as_longlong(d)) : U(0); }
+    __device__ static double value(U k) { return __longlong_as_double((long long)k); }
+};
+template <>
+struct BKey<float> {
+    using U = unsigned int;
+    static constexpr bool dbl = false;
+    static constexpr int mbits = 23, bias = 150;
+    __device__ static U key(float d) { return d > 0.0f ? U(__float_as_uint(d)) : U(0); }
+    __device__ static double value(U k) { return double(__uint_as_float(k)); }
+};
+
+// integer significand m and exponent e of a key: value = m 2^e
+template <class K>
+__device__ inline unsigned long long key_significand(typename K::U k)
+{
+    using U = typename K::U;
+    const U e = k >> K::mbits;
+    return (unsigned long long)((k & ((U(1) << K::mbits) - 1)) | (e ? (U(1) << K::mbits) : U(0)));
+}
+template <class K>
+__device__ inline int key_exponent(typename K::U k)
+{
+    const int e = int(k >> K::mbits);
+    return (e ? e : 1) - K::bias;
+}
+
+// One level of the budget selection: per tile, a histogram of the digit
+// (count and exact significand sum per bucket) of the values whose higher
+// digits match the prefix, added into the domain's histogram.  Each thread
+// walks one column of the tile and merges runs of equal buckets in registers
+// first (at most kMaxTileH values: the significand sum stays below 2^59).
+template <class A, bool CAV>
+__global__ void __launch_bounds__(kThreads) k_budget_hist(StepArgs a, int level)
+{
+    using K = BKey<A>;
+    using U = typename K::U;
+    __shared__ unsigned hn[kBudgetBuckets];
+    __shared__ unsigned long long hlo[kBudgetBuckets];
+    __shared__ unsigned hhi[kBudgetBuckets];
+    const Tile t = a.tiles[blockIdx.x];
+    const DomainDev& D = a.dom[t.domain];
+    if (!(D.limiter & kLimEnsBudget) || D.bstate->done) return;
+    const unsigned long long prefix = D.bstate->prefix;
+    const int lo = budget_lo(K::dbl, level), hi = budget_hi(K::dbl, level);
+    const U dmask = (U(1) << (hi - lo)) - 1;
+    for (int k = threadIdx.x; k < kBudgetBuckets; k += kThreads) {
+        hn[k] = 0;
+        hlo[k] = 0;
+        hhi[k] = 0;
+    }
+    __syncthreads();
+    const int x = t.x0 + int(threadIdx.x);
+    auto flush = [&](int b, unsigned cnt, unsigned long long sum) {
+        atomicAdd(&hn[b], cnt);
+        const unsigned long long old = atomicAdd(&hlo[b], sum);
+        if (old + sum < old) atomicAdd(&hhi[b], 1u);
+    };
+    if (x < t.x1) {
+        const A* ds = static_cast<const A*>(D.dsbuf);
+        int cur = -1;
+        unsigned cnt = 0;
+        unsigned long long sum = 0;
+        for (int y = t.y0; y < t.y1; ++y) {
+            if (CAV && (x == 0 || x == D.nx - 1 || y == 0 || y == D.ny - 1)) continue;   // walls and lid
+            const A d = ds[(long long)y * D.nx + x];
+            if (!isfinite(d)) continue;
+            const U k = K::key(d);
+            if ((unsigned long long)(k >> hi) != prefix) continue;
+            const int b = int((k >> lo) & dmask);
+            if (b != cur) {
+                if (cnt) flush(cur, cnt, sum);
+                cur = b;
+                cnt = 0;
+                sum = 0;
+            }
+            ++cnt;
+            sum += key_significand<K>(k);
+        }
+        if (cnt) flush(cur, cnt, sum);
+    }
+    __syncthreads();
+    BudgetBucket* gh = D.bhist;
+    for (int k = threadIdx.x; k < kBudgetBuckets; k += kThreads)
+        if (hn[k]) {
+            atomicAdd(&gh[k].n, (unsigned long long)hn[k]);
+            const unsigned long long old = atomicAdd(&gh[k].lo, hlo[k]);
+            const unsigned long long hiadd = (unsigned long long)hhi[k] + (old + hlo[k] < old ? 1ull : 0ull);
+            if (hiadd) atomicAdd(&gh[k].hi, hiadd);
+        }
+}
+
+// One level of the budget selection, one workgroup per domain.  With
+// g(t) = sum over values v > t of (v - t), decreasing in t, the threshold
+// solves g(Delta S_0) = budget; it lies in the highest bucket whose lower
+// edge L has g(L) >= budget.  That bucket's digit extends the prefix; at the
+// last level the bucket is a single value v, g is linear above it, and
+// Delta S_0 = (sum of the values above v - budget) / (their count).  The
+// histogram is read in a fixed order and left zero for the next level.
+template <class A>
+__global__ void __launch_bounds__(kThreads) k_budget_select(StepArgs a, int level)
+{
+    using K = BKey<A>;
+    using U = typename K::U;
+    constexpr int per = kBudgetBuckets / kThreads;
+    __shared__ double ts[kThreads], tc[kThreads];
+    __shared__ int best;
+    const DomainDev& D = a.dom[blockIdx.x];
+    if (!(D.limiter & kLimEnsBudget)) return;
+    BudgetState* bs = D.bstate;
+    if (bs->done) return;
+    const int tid = int(threadIdx.x);
+    const unsigned long long prefix = bs->prefix;
+    const int lo = budget_lo(K::dbl, level), hi = budget_hi(K::dbl, level);
+    const int w = hi - lo;
+    auto edge_of = [&](int b) { return U(((prefix << w) | (unsigned long long)b) << lo); };
+    double s[per], c[per];
+    double my_s = 0.0, my_c = 0.0;
+#pragma unroll
+    for (int i = per - 1; i >= 0; --i) {
+        const int b = tid * per + i;
+        BudgetBucket& gb = D.bhist[b];
+        const unsigned long long n = gb.n, l = gb.lo, h = gb.hi;
+        gb.n = 0;
+        gb.lo = 0;
+        gb.hi = 0;
+        c[i] = double(n);
+        s[i] = n ? ldexp(double(h) * 18446744073709551616.0 + double(l), key_exponent<K>(edge_of(b))) : 0.0;
+        my_s += s[i];
+        my_c += c[i];
+    }
+    ts[tid] = my_s;
+    tc[tid] = my_c;
+    if (tid == 0) best = -1;
+    __syncthreads();
+    if (tid == 0) {
+        // sums above each thread's buckets, from the top down
+        double rs = bs->s_above, rc = bs->c_above;
+        for (int k = kThreads - 1; k >= 0; --k) {
+            const double vs = ts[k], vc = tc[k];
+            ts[k] = rs;
+            tc[k] = rc;
+            rs += vs;
+            rc += vc;
+        }
+    }
+    __syncthreads();
+    const double budget = bs->budget;
+    const int nb = 1 << w;   // buckets of this digit (the rest stay empty)
+    double S = ts[tid], C = tc[tid];
+    double sa = 0.0, ca = 0.0, sa0 = 0.0, ca0 = 0.0;
+    int mine = -1;
+#pragma unroll
+    for (int i = per - 1; i >= 0; --i) {
+        const int b = tid * per + i;
+        const double L = b < nb ? K::value(edge_of(b)) : 0.0;
+        if (i == 0) {
+            sa0 = S;
+            ca0 = C;
+        }
+        const double S1 = S + s[i], C1 = C + c[i];
+        if (mine < 0 && b < nb && S1 - L * C1 >= budget) {
+            mine = b;
+            sa = S;
+            ca = C;
+        }
+        S = S1;
+        C = C1;
+    }
+    if (mine >= 0) atomicMax(&best, mine);
+    __syncthreads();
+    int j = best;
+    if (j < 0 && level == 0) {
+        // the budget exceeds g(0) = sum Delta S: every node goes to f*
+        if (tid == 0) {
+            D.ens[kEBudget] = fmax(0.0, D.delta_ens);
+            bs->done = 1;
+        }
+        return;
+    }
+    if (j < 0) {
+        // the lower edge of the parent bucket met the condition; rounding in
+        // the regrouped sums may put it just below here: keep its lowest bucket
+        j = 0;
+        mine = tid == 0 ? 0 : -1;
+        sa = sa0;
+        ca = ca0;
+    }
+    if (mine != j) return;
+    bs->prefix = (prefix << w) | (unsigned long long)j;
+    bs->s_above = sa;
+    bs->c_above = ca;
+    bs->level = level + 1;
+    if (level + 1 == budget_levels(K::dbl)) {
+        const double v = K::value(edge_of(j));
+        const double t0 = ca > 0.0 ? (sa - budget) / ca : v;
+        D.ens[kEBudget] = fmax(fmax(t0, 0.0), D.delta_ens);
+        bs->done = 1;
+    }
+}
+
+hipError_t launch_budget(int storage, int bc, const StepArgs& a, hipStream_t s)
+{
+    const bool dbl = storage == kF64;
+    for (int level = 0; level < budget_levels(dbl); ++level) {
+        if (dbl) {
+            if (bc == kCavity)
+                hipLaunchKernelGGL((k_budget_hist<double, true>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
+            else
+                hipLaunchKernelGGL((k_budget_hist<double, false>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
+            hipLaunchKernelGGL(k_budget_select<double>, dim3(a.ndomains), dim3(kThreads), 0, s, a, level);
+        } else {
+            if (bc == kCavity)
+                hipLaunchKernelGGL((k_budget_hist<float, true>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
+            else
+                hipLaunchKernelGGL((k_budget_hist<float, false>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
+            hipLaunchKernelGGL(k_budget_select<float>, dim3(a.ndomains), dim3(kThreads), 0, s, a, level);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s)

@@ -48,7 +48,7 @@ struct DomainHost {
     long long plane = 0;
     size_t n = 0;
     size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0, off_dsbuf = 0;
-    size_t off_ens = 0, off_phibuf = 0;
+    size_t off_ens = 0, off_phibuf = 0, off_bstate = 0, off_bhist = 0;
     bool dsbuf = false, phibuf = false;
     double shift = 0;
     int tile_first = 0, tile_count = 0;
@@ -79,6 +79,7 @@ struct lbm_ctx {
     int ntiles = 0;
     bool median_pass = false;   // D2Q9 with the median filter in some domain
     bool ens_pass = false;      // an ensemble-dependent limiter in some domain
+    bool budget = false;        // the budget threshold in some domain
     long long steps_done = 0, finalized_for = -1;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -141,8 +142,6 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
                 return fail(nullptr, LBM_EINVAL, where + "ensemble limiter needs finite ens_c >= 0, ens_k > 0, delta_ens >= 0");
             if ((d.limiter & LBM_LIM_ENS_RATIONAL) && !(d.ens_c > 0.0 && d.ens_k >= 0.5))
                 return fail(nullptr, LBM_EINVAL, where + "rational limiter needs ens_c > 0 and ens_k >= 1/2");
-            if (d.limiter & LBM_LIM_ENS_BUDGET)
-                return fail(nullptr, LBM_EINVAL, where + "the budget threshold is not available on the GPU path");
         }
         if (d.trim_mode != 0 && d.trim_mode != 1) return fail(nullptr, LBM_EINVAL, where + "bad trim_mode");
         if (d.median_mode != 0 && d.median_mode != 1) return fail(nullptr, LBM_EINVAL, where + "bad median_mode");
@@ -244,6 +243,12 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         }
         h.off_ens = off;
         off = align_up(off + kNEns * sizeof(double), kAlign);
+        if (h.d.limiter & kLimEnsBudget) {
+            h.off_bstate = off;
+            off = align_up(off + sizeof(BudgetState), kAlign);
+            h.off_bhist = off;
+            off = align_up(off + kBudgetBuckets * sizeof(BudgetBucket), kAlign);
+        }
         const int min_h = run->tile_h > 0 ? run->tile_h : kMaxTileH;
         const int tiles = h.d.lattice == LBM_D2Q9 ? strips_of(h.d.nx) * ((h.d.ny + min_h - 1) / min_h)
                                                   : (h.d.nx + k1DWidth - 1) / k1DWidth;
@@ -350,6 +355,9 @@ int upload_domains(lbm_ctx* ctx)
         d.ens_c = h.d.ens_c;
         d.ens_k = h.d.ens_k;
         d.delta_ens = h.d.delta_ens;
+        const bool budget = h.d.limiter & kLimEnsBudget;
+        d.bstate = budget ? reinterpret_cast<BudgetState*>(ctx->ws + h.off_bstate) : nullptr;
+        d.bhist = budget ? reinterpret_cast<BudgetBucket*>(ctx->ws + h.off_bhist) : nullptr;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_dom(), dd.data(), dd.size() * sizeof(DomainDev), hipMemcpyHostToDevice,
                                 ctx->stream));
@@ -379,6 +387,7 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.ndomains = int(ctx->dom.size());
     a.median_pass = (ctx->median_pass || ctx->ens_pass) ? 1 : 0;
     a.ens_pass = ctx->ens_pass ? 1 : 0;
+    a.budget = ctx->budget ? 1 : 0;
     a.rows = ctx->d_rows();
     a.nrows = ctx->lay.nrows;
     a.rowpart = ctx->d_rowpart();
@@ -405,6 +414,7 @@ int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
     // ensemble limiters: E(Delta S') of this step first (Sec. 3.3, 3.4)
     if (e == hipSuccess && ctx->ens_pass) e = launch_ens_prepare(a, ctx->stream);
+    if (e == hipSuccess && ctx->budget) e = launch_budget(ctx->storage, ctx->bc, a, ctx->stream);
     if (e == hipSuccess && (ctx->median_pass || ctx->ens_pass)) {
         if (ctx->lattice == LBM_D2Q9)
             e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
@@ -595,6 +605,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     for (const auto& h : ctx->dom) {
         ctx->median_pass = ctx->median_pass || (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN));
         ctx->ens_pass = ctx->ens_pass || (h.d.limiter & kLimEns);
+        ctx->budget = ctx->budget || (h.d.limiter & kLimEnsBudget);
     }
 
     auto bail = [&](int code) {
@@ -625,6 +636,14 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         }
         ctx->own_ws = true;
     }
+
+    // budget histograms start zero; every selection level leaves them zero
+    for (const auto& h : ctx->dom)
+        if (h.d.limiter & kLimEnsBudget) {
+            e = hipMemsetAsync(ctx->ws + h.off_bhist, 0, kBudgetBuckets * sizeof(BudgetBucket), ctx->stream);
+            if (e != hipSuccess)
+                return bail(fail(nullptr, LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));
+        }
 
     // initial state f(x, 0) in FP64, converted into buffer 0
     double* stage = ctx->d_stage();

@@ -35,6 +35,36 @@ enum {
 // per-domain ensemble values of the current step (device array of kNEns doubles)
 enum { kEMean = 0, kEThresh, kESmoothA, kEBudget, kNEns };
 
+// Entropy-budget threshold (eq. EntThresh) by radix selection over the bit
+// patterns of the non-negative Delta S' values, most significant digit
+// first.  Each level histograms one digit of the values whose higher digits
+// equal the prefix chosen so far.  A bucket holds values of one binary
+// exponent, so its sum is kept exactly as the integer sum of the
+// significands: the histogram does not depend on the order of the additions,
+// and neither does the threshold.
+constexpr int kBudgetBuckets = 2048;
+struct BudgetState {
+    unsigned long long prefix;   // digits chosen so far
+    double budget;               // delta_0 [1 - (2 beta - 1)^2] sum Delta S'
+    double s_above, c_above;     // sum and count of the values above the chosen bucket
+    int level, done;
+};
+struct BudgetBucket {
+    unsigned long long n, lo, hi;   // count; significand sum = hi 2^64 + lo
+};
+// key digits: FP64 keys 11 bits (the exponent), 11, 11, 10, 10, 10; FP32 keys
+// 11 bits (the exponent and 3 significand bits), 10, 10
+__host__ __device__ constexpr int budget_levels(bool dbl) { return dbl ? 6 : 3; }
+__host__ __device__ constexpr int budget_lo(bool dbl, int level)
+{
+    return dbl ? (level == 0 ? 52 : level == 1 ? 41 : level == 2 ? 30 : level == 3 ? 20 : level == 4 ? 10 : 0)
+               : (level == 0 ? 20 : level == 1 ? 10 : 0);
+}
+__host__ __device__ constexpr int budget_hi(bool dbl, int level)   // one past the digit's top bit
+{
+    return level == 0 ? (dbl ? 63 : 31) : budget_lo(dbl, level - 1);
+}
+
 // Per-domain parameters, device visible.  Pointers are device pointers.
 struct DomainDev {
     void* buf[2];           // population planes (storage type), A and B
@@ -55,6 +85,8 @@ struct DomainDev {
     void* phibuf;                 // D1Q3 with ensemble limiters: phi applied by the first pass
     int strips;                   // D2Q9: column strips of kThreads columns
     int row_first, row_count;     // D2Q9: this domain's range in the row table
+    BudgetState* bstate;          // budget threshold: search state (budget limiter only)
+    BudgetBucket* bhist;          // [kBudgetBuckets], left zero between levels
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
     void* dsbuf;            // [ny*nx] Delta S' of the last collision (arithmetic type), median only
 };
@@ -93,6 +125,7 @@ struct StepArgs {
                             // (set 0: collision, set 1: median pass)
     int median_pass;        // 1 if a second pass (median and/or ensemble limiters) writes set 1
     int ens_pass;           // 1 if some domain has an ensemble-dependent limiter
+    int budget;             // 1 if some domain has the budget threshold
     const Tile* rows;       // D2Q9 row segments in row-major order, one per collision workgroup
     int nrows;              // the D2Q9 collision grid has nrows blocks
     double* rowpart;        // [nrows][kNStat]: collision partials of the last step
@@ -106,6 +139,8 @@ hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a,
 hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
 // E(Delta S') and ensemble thresholds of the step just run (before the second pass)
 hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s);
+// the budget threshold of the step just run (after launch_ens_prepare)
+hipError_t launch_budget(int storage, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);
 hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u, double* f, int nx, int ny,
                          hipStream_t s);

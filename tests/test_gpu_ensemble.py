@@ -15,7 +15,7 @@ from tests.gpu_util import DS_NOISE, Pair, assert_ds_close, assert_masks_equal, 
 pytestmark = pytest.mark.gpu
 
 D1Q3, D2Q9 = 1, 2
-THRESH, SMOOTH, RATIONAL = 4, 8, 16
+THRESH, SMOOTH, RATIONAL, BUDGET = 4, 8, 16, 32
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -37,6 +37,9 @@ CASES = [
     (RATIONAL, dict(ens_c=2.0, ens_k=1.0)),
     (THRESH | 3, dict(ens_c=3.0)),
     (SMOOTH | RATIONAL | THRESH | 1, dict(ens_c=4.0, ens_k=1.0, delta_ens=0.02)),
+    (BUDGET, dict(ens_c=0.3)),
+    (BUDGET, dict(ens_c=0.05, delta_ens=1e-4)),
+    (BUDGET | 2, dict(ens_c=0.9)),
 ]
 
 
@@ -55,7 +58,8 @@ def test_d2q9_periodic_single_step_fp64(limiter, kw, ds):
     assert_stats_close(pr)
 
 
-@pytest.mark.parametrize("limiter,kw", [(THRESH, dict(ens_c=5.0)), (SMOOTH, dict(ens_k=0.5, delta_ens=0.01))])
+@pytest.mark.parametrize("limiter,kw", [(THRESH, dict(ens_c=5.0)), (SMOOTH, dict(ens_k=0.5, delta_ens=0.01)),
+                                        (BUDGET, dict(ens_c=0.5))])
 def test_cavity_multistep_fp64(limiter, kw):
     """64 x 64 cavity from rest (Re = 3000 scaled), an ensemble limiter
     combined with the median filter, 60 steps."""
@@ -75,7 +79,7 @@ def test_cavity_multistep_fp64(limiter, kw):
 
 @pytest.mark.parametrize("limiter,kw", [(THRESH, dict(ens_c=5.0)), (THRESH, dict(ens_c=20.0)),
                                         (SMOOTH, dict(ens_k=0.5, delta_ens=0.01)),
-                                        (RATIONAL, dict(ens_c=3.0, ens_k=1.0))])
+                                        (RATIONAL, dict(ens_c=3.0, ens_k=1.0)), (BUDGET, dict(ens_c=0.5))])
 def test_shock_tube_fp64(limiter, kw):
     """The shock-tube runs of Sec. 4.3.2 (800 sites, nu = 1e-9, entropic
     f*, tube ends), 100 steps from the 1:2 density step."""
@@ -137,3 +141,36 @@ def test_reduced_precision_smooth_limiter(storage):
     scale = np.abs(pr.fo).max()
     tol = 1e-6 if storage == 1 else 3e-3
     assert np.abs(pr.f - pr.fo).max() <= tol * scale
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("frac", [0.0, 0.02, 0.4, 1.0, 50.0])
+def test_budget_threshold(storage, frac):
+    """eq. (EntThresh) on the device: the threshold against the oracle's exact
+    solution on the empirical distribution, from no budget (the threshold at
+    the largest value) to a budget beyond sum Delta S' (every node to f*).
+    FP32 storage takes the decision on FP32 Delta S' values, so there only
+    the threshold's defining equation is checked, on the device's values."""
+    L = lbm()
+    f0 = wl.random_populations(9, 520, 90, seed=31, amp=0.03, spike_frac=0.05, spike_amp=0.35)
+    dom = L.Domain(lattice=D2Q9, nx=520, ny=90, beta=0.9, qe=0, ds_form=1, limiter=BUDGET, ens_c=frac)
+    pr = Pair(dom, f0, steps=1, storage=storage)
+    t = pr.stats["ens_threshold"]
+    say(f"[budget] frac {frac} threshold gpu {t!r} oracle {pr.so['ens_threshold']!r} moved {pr.stats['n_ensemble']}")
+    if storage == 0:
+        assert t == pytest.approx(pr.so["ens_threshold"], rel=1e-12, abs=1e-300)
+        assert_masks_equal(pr)
+        fields_close(pr)
+        assert_stats_close(pr)
+    else:
+        d = pr.ds.astype(np.float32).astype(np.float64).ravel()
+        c = 2 * 0.9 - 1
+        budget = frac * (1 - c * c) * pr.stats["sum_dS_post"]
+        if frac == 0.0:
+            assert t == pytest.approx(d.max(), rel=1e-7)
+        elif budget >= d.sum():
+            assert t == 0.0
+        else:
+            assert np.maximum(d - t, 0).sum() == pytest.approx(budget, rel=1e-6)
+        # the device compares Delta S' with the threshold rounded to FP32
+        assert pr.stats["n_ensemble"] == int((d > float(np.float32(t))).sum())
