@@ -17,9 +17,11 @@ roofline of the whole step, and the FP64 CPU oracle timed on the host on a
 1024 x 1024 replica of the same workload.
 
 --variants adds the reduced-precision runs (FP16 / BF16 shifted storage on
-an 8192 x 8192 double shear layer, against FP32 on the same input) and the
-batched ensemble of 256 lid-driven cavities (one launch per step for all of
-them, against the same cavities run one by one).
+an 8192 x 8192 double shear layer, against FP32 on the same input), the
+headline step with the median filter active in every tile, the headline step
+with each ensemble-dependent limiter added, and the batched ensemble of 256
+lid-driven cavities (one launch per step for all of them, against the same
+cavities run one by one).
 
 --summarize-pmc FETCH_CSV WRITE_CSV turns two rocprofv3 --pmc runs of this
 script (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy) into the HBM
@@ -169,6 +171,30 @@ def variants(torch, L, wl, stream, args):
             "collide_ms": round(k1, 5), "median_ms": round(k2, 5),
             "filtered_fraction": round(st["n_filtered"] / sites, 4), "steps": steps}
     res["median_active_4096"] = act
+
+    # the headline grid with each ensemble-dependent limiter added to trimming
+    # and the median filter: E(Delta S') reduced every step, then (budget) the
+    # radix selection of the threshold, then the second pass with the factors
+    print("[bench] variant 4096^2 with ensemble-dependent limiters", file=sys.stderr, flush=True)
+    ens = {}
+    for name, lim, kw in (("threshold_cE", L.LBM_LIM_ENS_THRESHOLD, dict(ens_c=5.0)),
+                          ("smooth_k0.5", L.LBM_LIM_ENS_SMOOTH, dict(ens_k=0.5, delta_ens=0.01)),
+                          ("rational_k1", L.LBM_LIM_ENS_RATIONAL, dict(ens_c=2.0, ens_k=1.0)),
+                          ("budget", L.LBM_LIM_ENS_BUDGET, dict(ens_c=0.05))):
+        dom = c2_domain(L, wl, 4096)
+        dom.limiter |= lim
+        for k, v in kw.items():
+            setattr(dom, k, v)
+        with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
+            ms = time_steps(torch, L, ctx, stream, steps, 16)
+            st = L.lbm_entropy_stats(ctx)
+            k1, k2 = L.lbm_kernel_times(ctx, 20)
+        sites = dom.nx * dom.ny
+        ens[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
+                     "collide_ms": round(k1, 5), "rest_ms": round(k2, 5),
+                     "moved_fraction": round(st["n_ensemble"] / sites, 4),
+                     "threshold": st["ens_threshold"], "mean_dS": st["mean_dS"], "steps": steps}
+    res["ensemble_limiters_4096"] = ens
 
     print("[bench] variant cavity ensemble (256 domains)", file=sys.stderr, flush=True)
     batch = wl.cavity_batch(256)
