@@ -28,7 +28,8 @@ enum {
     kSJx, kSJy,
     kSDpre, kSDpost, kSMax, kSLim, kSEnt,
     kSTrim, kSFilt, kSNonpos, kSNonfin, kSFluid,
-    kSAbove,      // fluid nodes with Delta S' > delta_median (median filter candidates)
+    kSAbove,      // median candidates (Delta S' > delta_median); in a collision partial: bit w set
+                  // when wave w of the segment holds one (that wave stored its Delta S')
     kSEns         // nodes an ensemble-dependent limiter moved
 };
 

@@ -559,12 +559,14 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
             v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
         }
     }
-    const double cnt[7] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
-                           double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
-                           double(__popcll(__ballot(acc.fluid != 0))), double(__popcll(__ballot(acc.above != 0))),
-                           double(__popcll(__ballot(acc.ens != 0)))};
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
+    // kSAbove is not a count here: bit w is set when wave w holds a node above
+    // the median tolerance (the median pass reads which waves stored Delta S')
+    const double cnt[7] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
+                           double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
+                           double(__popcll(__ballot(acc.fluid != 0))), __ballot(acc.above != 0) ? double(1 << wave) : 0.0,
+                           double(__popcll(__ballot(acc.ens != 0)))};
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);

@@ -186,6 +186,13 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     const long long step = a.counter[a.parity];
     // the index of the next step, read by the next launch (which reads buffer 1 - parity)
     if (ridx == 0 && threadIdx.x == 0) a.counter[1 - a.parity] = step + 1;
+    // The ensemble limiters and the GATE reading of the median use every
+    // Delta S'.  The FLOOR median only needs the values above delta: its
+    // threshold max(median, delta) and its decision are unchanged when every
+    // value at or below delta is replaced by 0.  So there a wave with no node
+    // above delta stores nothing, and the median pass reads its 64 columns as
+    // zeros (the segment's partial records which waves stored).
+    const bool every = (D.limiter & kLimEns) || D.median_mode != 0;
     const Cols<T, BC> cl(t.x0 + int(threadIdx.x), nx, t.x0 + int(threadIdx.x) < t.x1);
     AccT<A> acc;
     if (cl.ok) {
@@ -215,8 +222,10 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                 const A phi = trim_phi(D, S.dpost, mask);
                 store_limited<T>(dst, plane, row, cl.own, S, phi, c);
                 if (keep_ds) {
-                    Store<A>::st(dsb + node, S.dpost);
-                    if ((D.limiter & kLimMedian) && S.dpost > A(D.delta_median)) acc.above = 1;
+                    // NaN counts as above: such a wave always stores its values
+                    const bool up = (D.limiter & kLimMedian) && !(S.dpost <= A(D.delta_median));
+                    if (up) acc.above = 1;
+                    if (every || __ballot(up) != 0) Store<A>::st(dsb + node, S.dpost);
                 }
                 if (mask & kMaskTrim) {
                     ++acc.trim;
@@ -370,13 +379,20 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             xp = x < nx - 1 ? x + 1 : x;
         }
         // rows y0-1 .. y1 are read; y1 <= ny, so one wrap keeps them in range
-        auto row_of = [&](int y) -> long long {
-            int yy;
+        auto row_of = [&](int y) -> int {
             if constexpr (BC == kPeriodic)
-                yy = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+                return y < 0 ? y + ny : (y >= ny ? y - ny : y);
             else
-                yy = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
-            return (long long)yy * nx;
+                return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        };
+        // FLOOR median only: the 64 columns of a collision wave in which no
+        // node exceeded delta hold no Delta S' of this step and read as zeros
+        // (bit w of a segment's count of such nodes: wave w stored)
+        const bool sparse = !((D.limiter & kLimEns) || D.median_mode != 0);
+        const int sx = x / kThreads, sxm = xm / kThreads, sxp = xp / kThreads;
+        const int wx = (x % kThreads) / kWave, wxm = (xm % kThreads) / kWave, wxp = (xp % kThreads) / kWave;
+        auto stored = [&](const double* rp, int strip, int w) {
+            return (int(rp[strip * kNStat]) >> w) & 1;
         };
         // Each lane loads its own column (one aligned load per row); the
         // columns x -+ 1 come from the neighbouring lanes.  Only the first
@@ -386,10 +402,17 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
         const bool own_l = lane == 0;
         const bool own_r = lane == kWave - 1 || x == t.x1 - 1;
         auto load_own = [&](int y, A (&r)[3]) {
-            const long long rr = row_of(y);
+            const int yy = row_of(y);
+            const long long rr = (long long)yy * nx;
             r[1] = Store<A>::ld(dsb + (rr + x));
             if (own_l) r[0] = Store<A>::ld(dsb + (rr + xm));
             if (own_r) r[2] = Store<A>::ld(dsb + (rr + xp));
+            if (sparse) {
+                const double* rp = a.rowpart + ((long long)D.row_first + (long long)yy * D.strips) * kNStat + kSAbove;
+                if (!stored(rp, sx, wx)) r[1] = A(0);
+                if (own_l && !stored(rp, sxm, wxm)) r[0] = A(0);
+                if (own_r && !stored(rp, sxp, wxp)) r[2] = A(0);
+            }
         };
         auto complete = [&](A (&r)[3]) {
             // every active lane takes part in the shifts (no branch around them)

@@ -236,10 +236,13 @@ def test_special_betas_and_zero_threshold(beta):
     assert_stats_close(pr)
 
 
-@pytest.mark.parametrize("tile", [16, None])
-def test_median_tiles_without_candidates(tile):
+@pytest.mark.parametrize("tile,steps,mode", [(16, 1, 0), (None, 1, 0), (None, 5, 0), (None, 5, 1)])
+def test_median_tiles_without_candidates(tile, steps, mode):
     """Spikes only in a band of rows: median tiles elsewhere have no node
-    above delta and skip their medians; results must not change."""
+    above delta and skip their medians, and (FLOOR reading) row segments with
+    no node above delta store no Delta S' and are read as zeros, also when
+    the plane still holds an earlier step's values there (several steps, the
+    band spreading); results must not change."""
     o = orc()
     rho, u = wl.random_flow(300, 140, seed=12, umax=0.05)
     f0 = o.init_equilibrium(o.make_params(lattice=2, nx=300, ny=140, qe=0), rho, u)
@@ -247,7 +250,8 @@ def test_median_tiles_without_candidates(tile):
     band = np.zeros((140, 300), dtype=bool)
     band[70:100, 20:140] = True
     f0 = np.where(band[None], spikes * (f0.sum(0) / spikes.sum(0))[None], f0)
-    pr = Pair(dom2d(nx=300, ny=140, qe=0, limiter=3, delta_trim=1e-2, delta_median=1e-6), f0, tile=tile)
+    pr = Pair(dom2d(nx=300, ny=140, qe=0, limiter=3, delta_trim=1e-2, delta_median=1e-6, median_mode=mode), f0,
+              tile=tile, steps=steps)
     assert pr.so["n_filtered"] > 0
     assert_masks_equal(pr)
     assert_ds_close(pr, 1e-12)
