@@ -197,7 +197,7 @@ enum { NODE_FLUID = 0, NODE_WALL = 1, NODE_LID = 2 };
 
 static int node_type(const orc_params* p, int x, int y)
 {
-    if (p->bc != ORC_BC_CAVITY) return NODE_FLUID;
+    if (p->bc != ORC_BC_CAVITY && p->bc != ORC_BC_CAVITY_DIFFUSIVE) return NODE_FLUID;
     if (x == 0 || x == p->nx - 1 || y == 0) return NODE_WALL;
     if (y == p->ny - 1) return NODE_LID;
     return NODE_FLUID;
@@ -219,7 +219,7 @@ static int check_params(const orc_params* p)
         if (!(p->delta_ens >= 0.0) || !(p->ens_c >= 0.0) || !(p->ens_k > 0.0)) return -1;
         if ((p->limiter & ORC_LIM_ENS_RATIONAL) && !(p->ens_c > 0.0 && p->ens_k >= 0.5)) return -1;
     }
-    if (p->bc == ORC_BC_CAVITY) {
+    if (p->bc == ORC_BC_CAVITY || p->bc == ORC_BC_CAVITY_DIFFUSIVE) {
         if (p->lattice != ORC_D2Q9 || p->nx < 4 || p->ny < 4) return -1;
     } else if (p->bc == ORC_BC_TUBE) {
         if (p->lattice != ORC_D1Q3 || p->nx < 2) return -1;
@@ -332,6 +332,54 @@ int orc_init_equilibrium(const orc_params* p, const double* rho,
     return 0;
 }
 
+/* ---- diffusive Maxwell walls (Sec. 4.4.2) --------------------------------
+ * A boundary node that is not a corner keeps the populations that arrived
+ * along the wall or from the fluid; those that point into the fluid (a
+ * positive component along the wall's inward normal) are replaced by
+ * gamma f*_i(1, u_wall), with gamma the ratio of the mass that arrived from
+ * the fluid (populations with a negative normal component) to the mass of
+ * those quasiequilibrium populations: the wall returns what it received,
+ * distributed as the quasiequilibrium of the wall's velocity.  The density of
+ * the wall's f* cancels in gamma, so it is 1.  The lid moves with (u0, 0),
+ * the other walls rest.  A corner reflects every population (there the rule
+ * coincides with bounce-back).  No collision at boundary nodes. */
+static void diffusive_wall(const orc_params* p, int x, int y, const double* fl, double* out)
+{
+    const int nx = p->nx, ny = p->ny;
+    if ((x == 0 || x == nx - 1) && (y == 0 || y == ny - 1)) {
+        for (int i = 0; i < 9; ++i) out[i] = fl[orc_opposite(ORC_D2Q9, i)];
+        return;
+    }
+    int mx = 0, my = 0;
+    double uw = 0.0;
+    if (y == 0) {
+        my = 1;
+    } else if (y == ny - 1) {
+        my = -1;
+        uw = p->lid_ux;
+    } else if (x == 0) {
+        mx = 1;
+    } else {
+        mx = -1;
+    }
+    double fs[9];
+    orc_equilibrium(ORC_D2Q9, p->qe, 1.0, uw, 0.0, fs);
+    double sum_in = 0.0, sum_arrived = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        int vx, vy;
+        orc_velocity(ORC_D2Q9, i, &vx, &vy);
+        const int d = vx * mx + vy * my;
+        if (d > 0) sum_in += fs[i];
+        if (d < 0) sum_arrived += fl[i];
+    }
+    const double gamma = sum_arrived / sum_in;
+    for (int i = 0; i < 9; ++i) {
+        int vx, vy;
+        orc_velocity(ORC_D2Q9, i, &vx, &vy);
+        out[i] = vx * mx + vy * my > 0 ? gamma * fs[i] : fl[i];
+    }
+}
+
 /* ---- one time step -------------------------------------------------------
  * eq. (lbgkLB): collide every fluid node toward f*, apply the limiter to the
  * post-collision state (eq. (LimGenF) with the trimming or median rule),
@@ -408,6 +456,12 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
             dpre[site] = 0.0;
             dpost[site] = 0.0;
             int type = node_type(p, x, y);
+            if (type != NODE_FLUID && p->bc == ORC_BC_CAVITY_DIFFUSIVE) {
+                diffusive_wall(p, x, y, fl, fp);
+                for (int i = 0; i < q; ++i) o[i * n + site] = fp[i];
+                m[site] = ORC_MASK_NOTFLUID;
+                continue;
+            }
             if (type == NODE_WALL) {
                 for (int i = 0; i < q; ++i)
                     o[i * n + site] = fl[orc_opposite(p->lattice, i)];

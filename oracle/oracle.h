@@ -48,7 +48,10 @@ enum { ORC_LIM_TRIM = 1, ORC_LIM_MEDIAN = 2, ORC_LIM_ENS_THRESHOLD = 4, ORC_LIM_
        ORC_LIM_ENS_RATIONAL = 16, ORC_LIM_ENS_BUDGET = 32 };
 enum { ORC_TRIM_HOMOTHETY = 0, ORC_TRIM_EHRENFEST = 1 };
 enum { ORC_MED_FLOOR = 0, ORC_MED_GATE = 1 };
-enum { ORC_BC_PERIODIC = 0, ORC_BC_CAVITY = 1, ORC_BC_TUBE = 2 };
+/* boundaries: periodic; lid-driven cavity with on-node bounce-back walls and
+ * an equilibrium lid (Sec. 4.4.1); 1-D tube with reflecting ends (Sec. 4.3);
+ * lid-driven cavity with diffusive Maxwell walls (Sec. 4.4.2) */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_CAVITY = 1, ORC_BC_TUBE = 2, ORC_BC_CAVITY_DIFFUSIVE = 3 };
 
 /* mask bits written per node by orc_step */
 enum { ORC_MASK_TRIM = 1, ORC_MASK_MEDIAN = 2, ORC_MASK_NONPOS = 4,

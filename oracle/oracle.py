@@ -24,7 +24,7 @@ LIM_TRIM, LIM_MEDIAN = 1, 2
 LIM_ENS_THRESHOLD, LIM_ENS_SMOOTH, LIM_ENS_RATIONAL, LIM_ENS_BUDGET = 4, 8, 16, 32
 TRIM_HOMOTHETY, TRIM_EHRENFEST = 0, 1
 MED_FLOOR, MED_GATE = 0, 1
-BC_PERIODIC, BC_CAVITY, BC_TUBE = 0, 1, 2
+BC_PERIODIC, BC_CAVITY, BC_TUBE, BC_CAVITY_DIFFUSIVE = 0, 1, 2, 3
 MASK_TRIM, MASK_MEDIAN, MASK_NONPOS, MASK_NOTFLUID, MASK_ENSEMBLE = 1, 2, 4, 8, 16
 
 
