@@ -94,8 +94,13 @@ enum lbm_medmode { LBM_MED_FLOOR_DELTA = 0, LBM_MED_GATE_DELTA = 1 };
 enum lbm_dsform { LBM_DS_EXACT = 0, LBM_DS_QUADRATIC = 1 };
 /* boundaries: periodic; lid-driven cavity with on-node bounce-back walls and
  * a constant equilibrium lid (Sec. 4.4.1); 1-D tube with half-way
- * bounce-back ends (Sec. 4.3) */
-enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_CAVITY = 1, LBM_BC_TUBE_ENDS = 2 };
+ * bounce-back ends (Sec. 4.3); lid-driven cavity with diffusive Maxwell walls
+ * (Sec. 4.4.2): a non-corner boundary node keeps what free flight brought,
+ * except the populations pointing into the fluid, which become
+ * gamma f*_i(1, u_wall) with gamma = (mass that arrived from the fluid) /
+ * (mass of those f*_i); the lid moves with (lid_ux, 0), the other walls rest,
+ * corners reflect every population; boundary nodes do not collide. */
+enum lbm_bc { LBM_BC_PERIODIC = 0, LBM_BC_CAVITY = 1, LBM_BC_TUBE_ENDS = 2, LBM_BC_CAVITY_DIFFUSIVE = 3 };
 /* population storage.  F64 stores f.  The others store the shift
  * g_i = f_i - w_i rho0 (w_i the lattice weights at rest) and compute in FP32;
  * global reductions are FP64 in every mode. */

@@ -29,6 +29,8 @@ constexpr int k1DWidth = kThreads - 2;    // output sites of one D1Q3 workgroup
 // D2Q9 tiles: kThreads consecutive columns
 int strips_of(int nx) { return (nx + kThreads - 1) / kThreads; }
 
+bool is_cavity(int bc) { return bc == LBM_BC_CAVITY || bc == LBM_BC_CAVITY_DIFFUSIVE; }
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int q_of(int lattice) { return lattice == LBM_D2Q9 ? 9 : 3; }
@@ -154,9 +156,9 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
                 return fail(nullptr, LBM_EINVAL, where + "D1Q3 supports periodic or tube ends");
             if (d.bc == LBM_BC_TUBE_ENDS && d.nx < 2) return fail(nullptr, LBM_EINVAL, where + "tube needs nx >= 2");
         } else {
-            if (d.bc != LBM_BC_PERIODIC && d.bc != LBM_BC_CAVITY)
+            if (d.bc != LBM_BC_PERIODIC && !is_cavity(d.bc))
                 return fail(nullptr, LBM_EINVAL, where + "D2Q9 supports periodic or cavity");
-            if (d.bc == LBM_BC_CAVITY && (d.nx < 4 || d.ny < 4))
+            if (is_cavity(d.bc) && (d.nx < 4 || d.ny < 4))
                 return fail(nullptr, LBM_EINVAL, where + "cavity needs nx, ny >= 4");
         }
         if (!(d.beta >= 0.0 && d.beta <= 1.0)) return fail(nullptr, LBM_EINVAL, where + "beta must be in [0, 1]");
@@ -164,11 +166,11 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
             return fail(nullptr, LBM_EINVAL, where + "delta must be finite and >= 0");
         if (!(d.rho0 > 0.0) || !finite(d.rho0)) return fail(nullptr, LBM_EINVAL, where + "rho0 must be finite and > 0");
         if (!finite(d.lid_ux)) return fail(nullptr, LBM_EINVAL, where + "lid_ux not finite");
-        if (d.qe == LBM_QE_ENTROPIC && d.bc == LBM_BC_CAVITY && std::fabs(d.lid_ux) >= 1.0)
+        if (d.qe == LBM_QE_ENTROPIC && is_cavity(d.bc) && std::fabs(d.lid_ux) >= 1.0)
             return fail(nullptr, LBM_EINVAL, where + "entropic f* needs |lid_ux| < 1");
         if (d.probe_x >= 0 || d.probe_y >= 0) {
             const bool in = d.probe_x >= 0 && d.probe_x < d.nx && d.probe_y >= 0 && d.probe_y < d.ny;
-            const bool fluid = d.bc != LBM_BC_CAVITY ||
+            const bool fluid = !is_cavity(d.bc) ||
                                (d.probe_x >= 1 && d.probe_x <= d.nx - 2 && d.probe_y >= 1 && d.probe_y <= d.ny - 2);
             if (!in || !fluid) return fail(nullptr, LBM_EINVAL, where + "probe must be a fluid node of the grid");
         }
@@ -355,6 +357,7 @@ int upload_domains(lbm_ctx* ctx)
         d.ens_c = h.d.ens_c;
         d.ens_k = h.d.ens_k;
         d.delta_ens = h.d.delta_ens;
+        d.diffusive = h.d.bc == LBM_BC_CAVITY_DIFFUSIVE ? 1 : 0;
         const bool budget = h.d.limiter & kLimEnsBudget;
         d.bstate = budget ? reinterpret_cast<BudgetState*>(ctx->ws + h.off_bstate) : nullptr;
         d.bhist = budget ? reinterpret_cast<BudgetBucket*>(ctx->ws + h.off_bhist) : nullptr;
@@ -596,7 +599,8 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     ctx->lattice = domains[0].lattice;
     ctx->qe = domains[0].qe;
     ctx->ds = domains[0].ds_form;
-    ctx->bc = domains[0].bc;
+    // both cavity kinds run the cavity kernels; the wall rule is per domain
+    ctx->bc = is_cavity(domains[0].bc) ? kCavity : domains[0].bc;
     ctx->flags = run->flags;
     ctx->stats_every = run->stats_every;
     ctx->probe_cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;

@@ -76,6 +76,7 @@ struct DomainDev {
     double delta_trim, delta_median;
     double rho0, lid_ux;
     int limiter, trim_mode, median_mode;
+    int diffusive;          // cavity walls: 0 on-node bounce-back + equilibrium lid, 1 diffusive Maxwell
     int probe_x, probe_y, probe_cap;
     float* probe;           // [probe_cap][2]
     unsigned char* mask;    // [ny*nx] when recording

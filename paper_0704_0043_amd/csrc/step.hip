@@ -161,6 +161,35 @@ __device__ __forceinline__ void store_limited(gptr<T> dst, long long plane, long
     for (int i = 0; i < 9; ++i) Store<T>::st(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
 }
 
+// Diffusive Maxwell wall node (Sec. 4.4.2), inward normal (mx, my), wall
+// velocity (uw, 0): the populations pointing into the fluid become
+// gamma f*_i(1, u_wall), gamma = (mass that arrived from the fluid) / (mass of
+// those f*_i), the others keep what free flight brought.  No collision.
+template <class T, int QE>
+__device__ __forceinline__ void diffusive_wall(gptr<T> dst, long long plane, long long row, unsigned own,
+                                               const typename Store<T>::A (&g)[9], typename Store<T>::A shift,
+                                               int mx, int my, typename Store<T>::A uw)
+{
+    using A = typename Store<T>::A;
+    using L = Lat<kD2Q9>;
+    A E[9];
+    eq_excess<kD2Q9, QE>(uw, A(0), E);
+    A sum_in = A(0), sum_arrived = A(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int d = L::vx(i) * mx + L::vy(i) * my;
+        if (d > 0) sum_in += A(L::w(i)) * (A(1) + E[i]);
+        if (d < 0) sum_arrived += A(L::w(i)) * shift + g[i];
+    }
+    const A gamma = sum_arrived / sum_in;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int d = L::vx(i) * mx + L::vy(i) * my;
+        const A v = d > 0 ? gamma * (A(L::w(i)) * (A(1) + E[i])) - A(L::w(i)) * shift : g[i];
+        Store<T>::st(at_bytes(dst + (i * plane + row), own), v);
+    }
+}
+
 template <class T, int QE, int DS, int BC>
 __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
 {
@@ -237,7 +266,14 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                     to_global<double>(D.dS)[node] = double(S.dpost);
                 }
             } else {
-                if (cls == kNodeWall) {
+                const bool corner = (cl.x == 0 || cl.x == nx - 1) && (y == 0 || y == ny - 1);
+                if (D.diffusive && !corner) {
+                    // diffusive Maxwell wall; the lid moves with (u0, 0)
+                    const int mx = cl.x == 0 ? 1 : (cl.x == nx - 1 ? -1 : 0);
+                    const int my = y == 0 ? 1 : (y == ny - 1 ? -1 : 0);
+                    diffusive_wall<T, QE>(dst, plane, row, cl.own, g, shift, my != 0 ? 0 : mx, my,
+                                          y == ny - 1 ? A(D.lid_ux) : A(0));
+                } else if (cls == kNodeWall) {
                     // bounce-back: every population leaves reversed, no collision
 #pragma unroll
                     for (int i = 0; i < Q; ++i) Store<T>::st(at_bytes(dst + (i * plane + row), cl.own), g[L::opp(i)]);

@@ -32,7 +32,7 @@ LBM_LIM_ENS_THRESHOLD, LBM_LIM_ENS_SMOOTH, LBM_LIM_ENS_RATIONAL, LBM_LIM_ENS_BUD
 LBM_TRIM_HOMOTHETY, LBM_TRIM_EHRENFEST = 0, 1
 LBM_MED_FLOOR_DELTA, LBM_MED_GATE_DELTA = 0, 1
 LBM_DS_EXACT, LBM_DS_QUADRATIC = 0, 1
-LBM_BC_PERIODIC, LBM_BC_CAVITY, LBM_BC_TUBE_ENDS = 0, 1, 2
+LBM_BC_PERIODIC, LBM_BC_CAVITY, LBM_BC_TUBE_ENDS, LBM_BC_CAVITY_DIFFUSIVE = 0, 1, 2, 3
 LBM_F64, LBM_F32, LBM_F16_SHIFT, LBM_BF16_SHIFT = 0, 1, 2, 3
 LBM_MASK_TRIM, LBM_MASK_MEDIAN, LBM_MASK_NONPOS, LBM_MASK_NOTFLUID, LBM_MASK_ENSEMBLE = 1, 2, 4, 8, 16
 LBM_RUN_RECORD, LBM_RUN_ENTROPY, LBM_RUN_NO_GRAPH, LBM_RUN_NO_TUNE = 1, 2, 4, 8
