@@ -23,6 +23,10 @@ with each ensemble-dependent limiter added, and the batched ensemble of 256
 lid-driven cavities (one launch per step for all of them, against the same
 cavities run one by one).
 
+--hopf runs, instead of the benchmark, the first-Hopf-bifurcation experiment
+(a batch of 100 x 100 cavities with diffusive walls over a range of Re for
+5000 non-dimensional time units each) and prints its analysis.
+
 --summarize-pmc FETCH_CSV WRITE_CSV turns two rocprofv3 --pmc runs of this
 script (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy) into the HBM
 traffic record the roofline reports.
@@ -264,6 +268,11 @@ def summarize_pmc(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
+def np_arange_inclusive(a, b, c):
+    k = int(round((b - a) / c))
+    return [a + i * c for i in range(k + 1)]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +287,11 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--hopf", action="store_true",
+                    help="instead of the step benchmark: the first-Hopf-bifurcation experiment (diffusive walls)")
+    ap.add_argument("--hopf-re", default="6000:9000:250", help="Reynolds numbers, start:stop:step (inclusive)")
+    ap.add_argument("--hopf-units", type=float, default=5000.0, help="non-dimensional time units per run")
+    ap.add_argument("--hopf-n", type=int, default=100)
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
@@ -296,6 +310,13 @@ def main():
         sys.exit(1)
     torch.cuda.init()
     stream = torch.cuda.Stream()
+    if args.hopf:
+        from paper_0704_0043_amd import hopf
+        a, b, c = (float(v) for v in args.hopf_re.split(":"))
+        res = hopf.run(L, list(np_arange_inclusive(a, b, c)), n=args.hopf_n, time_units=args.hopf_units,
+                       stream=stream.cuda_stream)
+        print(json.dumps({"hopf": res}), flush=True)
+        return
     n = args.n
     dom = c2_domain(L, wl, n)
     print(f"[bench] creating {n}x{n} FP32 context", file=sys.stderr, flush=True)

@@ -1,0 +1,110 @@
+"""First Hopf bifurcation of the lid-driven cavity (Sec. 4.4.2).
+
+A batch of N x N cavities with diffusive Maxwell walls, entropic f*, density
+1, lid speed u0 and the median filter (delta = 1e-3), one per Reynolds
+number, runs in one context for T non-dimensional time units (T L / u0 steps)
+while the velocity at the node nearest (L/16, 13L/16) is recorded every step.
+From the last 1 % of each signal:
+
+  * the energy of eq. (energy): E_u = || sqrt(L / (u0 |u_sig|)) (u_sig - mean) ||_2,
+    i.e. E_u^2 = (L / u0) times the variance of u_sig (|u_sig| samples, one per
+    step, so |u_sig| u0 / L is the signal's non-dimensional duration);
+  * the critical Reynolds number: a Hopf bifurcation has E_u^2 growing
+    linearly in Re past it, so Re_c is where the least-squares line through
+    the oscillating runs crosses E_u^2 = 0;
+  * the dominant frequency: the largest peak of the amplitude spectrum of
+    u_sig - mean, in cycles per non-dimensional time unit.
+
+L is N (the length in Re = u0 N / nu); the signal is in lattice units.
+"""
+from __future__ import annotations
+
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import workloads as wl
+
+
+def probe_node(n: int) -> tuple:
+    """node nearest (L/16, 13L/16) with node i at i / (N - 1)"""
+    return int(round((n - 1) / 16)), int(round(13 * (n - 1) / 16))
+
+
+def energy(u_sig, length: float, u0: float) -> float:
+    """eq. (energy)"""
+    u = np.asarray(u_sig, dtype=np.float64)
+    return math.sqrt(length / (u0 * len(u))) * float(np.linalg.norm(u - u.mean()))
+
+
+def critical_reynolds(re, e2, frac: float = 0.05):
+    """Re where the least-squares line through the oscillating runs (E_u^2
+    above `frac` of the largest) meets E_u^2 = 0; returns (Re_c, slope,
+    the Re values used), or (nan, nan, []) with fewer than two such runs."""
+    re = np.asarray(re, dtype=np.float64)
+    e2 = np.asarray(e2, dtype=np.float64)
+    osc = e2 > frac * e2.max() if e2.size and e2.max() > 0 else np.zeros(e2.shape, dtype=bool)
+    if osc.sum() < 2:
+        return math.nan, math.nan, []
+    slope, icpt = np.polyfit(re[osc], e2[osc], 1)
+    return float(-icpt / slope), float(slope), [float(r) for r in re[osc]]
+
+
+def dominant_frequency(u_sig, length: float, u0: float) -> float:
+    """cycles per non-dimensional time unit of the largest spectral peak
+    (Hann window, mean removed, rest frequency excluded)"""
+    u = np.asarray(u_sig, dtype=np.float64)
+    u = (u - u.mean()) * np.hanning(len(u))
+    amp = np.abs(np.fft.rfft(u))
+    k = int(np.argmax(amp[1:])) + 1
+    dt = u0 / length                  # non-dimensional time per step
+    return k / (len(u) * dt)
+
+
+def hopf_domains(L, re_values, n: int = 100, u0: float = 0.1, delta: float = 1e-3, qe=None):
+    doms = []
+    px, py = probe_node(n)
+    for re in re_values:
+        rho, u = wl.cavity_rest(n, n, rho0=1.0)
+        doms.append(L.Domain(lattice=L.LBM_D2Q9, nx=n, ny=n, beta=wl.beta_from_nu(u0 * n / re),
+                             qe=L.LBM_QE_ENTROPIC if qe is None else qe, limiter=L.LBM_LIM_MEDIAN,
+                             ds_form=L.LBM_DS_EXACT, bc=L.LBM_BC_CAVITY_DIFFUSIVE, delta_median=delta,
+                             rho0=1.0, lid_ux=u0, rho_init=rho, u_init=u, probe=(px, py)))
+    return doms
+
+
+def run(L, re_values, n: int = 100, u0: float = 0.1, time_units: float = 5000.0, tail: float = 0.01,
+        storage: int = 0, stream=None, chunk: int = 200000, log=sys.stderr) -> dict:
+    """Run the batch and analyse the probe signals; prints progress to `log`."""
+    steps = int(round(time_units * n / u0))
+    keep = max(2, int(round(tail * steps)))
+    doms = hopf_domains(L, re_values, n, u0)
+    run_desc = L.Run(storage=storage, graph_chunk=100, probe_capacity=keep, tile_h=16,
+                     stream=stream if stream is not None else 0)
+    t0 = time.perf_counter()
+    out = {"n": n, "u0": u0, "time_units": time_units, "steps": steps, "signal_steps": keep,
+           "re": [float(r) for r in re_values], "probe": list(probe_node(n))}
+    with L.lbm_create(doms, run_desc) as ctx:
+        done = 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            L.lbm_step(ctx, k)
+            L.lbm_synchronize(ctx)
+            done += k
+            print(f"[hopf] {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=log, flush=True)
+        wall = time.perf_counter() - t0
+        sig = [L.lbm_probe_trace(ctx, k, keep) for k in range(len(doms))]
+        stats = [L.lbm_entropy_stats(ctx, k) for k in range(len(doms))]
+    e = [energy(s[:, 0], n, u0) for s in sig]
+    e2 = [v * v for v in e]
+    rec, slope, used = critical_reynolds(re_values, e2)
+    out.update({
+        "E_u": e, "E_u2": e2, "Re_c": rec, "slope": slope, "fit_re": used,
+        "frequency": [dominant_frequency(s[:, 0], n, u0) for s in sig],
+        "u_mean": [float(s[:, 0].mean()) for s in sig], "v_mean": [float(s[:, 1].mean()) for s in sig],
+        "n_filtered_last": [int(s["n_filtered"]) for s in stats],
+        "wall_s": wall, "mlups": len(doms) * n * n * steps / wall / 1e6,
+    })
+    return out
