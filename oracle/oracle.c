@@ -174,6 +174,63 @@ double orc_entropy(int32_t lattice, const double* f)
     return s;
 }
 
+/* ---- ELBM collision (eqs. (elbm), (elbmLB), (entropy_estimate)) -----------
+ * F(f) = (1 - beta) f + beta f~ with f~ = (1 - alpha) f + alpha f*, alpha the
+ * nontrivial root of S(f~) = S(f).  With the entropic f*, ln(f*_i / W_i) is a
+ * combination of the conserved quantities, so for every state g on the line
+ * through f and f* (they share the moments) S(f*) - S(g) = sum g ln(g / f*)
+ * = sum f*_i h(x_i(g)), x(g) = (g - f*) / f*.  The deviation of f~ is
+ * (1 - alpha) x, so the equation reads
+ *     sum f*_i h((1 - alpha) x_i) = sum f*_i h(x_i),
+ * the same equation as a difference of entropies, but one that keeps its
+ * precision when f is close to f*.  It is solved by bisection in alpha on
+ * [1, alpha_max] to 1e-15, where alpha_max is the positivity boundary of f~
+ * (the first population of f~ reaching 0); the lower end of the final
+ * bracket is returned, so the entropy does not decrease.  When the equation
+ * has no root short of alpha_max, the positivity rule: f~ stops on the
+ * positivity boundary (alpha = alpha_max). */
+
+/* h with its limit h(-1) = 1 (a population at exactly zero) */
+static double h_closed(double x)
+{
+    return x <= -1.0 ? 1.0 : orc_h(x);
+}
+
+double orc_elbm_alpha(int32_t q, const double* f, const double* fstar, int32_t* posrule)
+{
+    double x[9], target = 0.0, smax = INFINITY;
+    *posrule = 0;
+    for (int i = 0; i < q; ++i) {
+        x[i] = (f[i] - fstar[i]) / fstar[i];
+        if (x[i] > 0.0 && 1.0 / x[i] < smax) smax = 1.0 / x[i];
+    }
+    if (!isfinite(smax)) return 2.0;             /* f = f*: every alpha gives f */
+    int nonpos = 0;
+    for (int i = 0; i < q; ++i) {
+        if (x[i] <= -1.0) nonpos = 1;
+        target += fstar[i] * h_closed(x[i]);
+    }
+    /* in s = alpha - 1: G(s) = sum f* h(-s x) - target, G(0) < 0, increasing */
+    double g_max = -target;
+    for (int i = 0; i < q; ++i) g_max += fstar[i] * h_closed(-smax * x[i]);
+    if (nonpos || g_max < 0.0) {
+        /* no state of entropy S(f) on the non-negative part of the line (or f
+         * itself has no entropy): positivity rule */
+        *posrule = 1;
+        return 1.0 + smax;
+    }
+    double lo = 0.0, hi = smax;
+    while (hi - lo > 1e-15) {
+        const double mid = 0.5 * (lo + hi);
+        double g = -target;
+        for (int i = 0; i < q; ++i) g += fstar[i] * h_closed(-mid * x[i]);
+        if (g <= 0.0) lo = mid;
+        else hi = mid;
+        if (mid == lo && mid == hi) break;
+    }
+    return 1.0 + lo;
+}
+
 /* Sec. 3.5: sort the neighbourhood, take the middle value. */
 double orc_median(const double* v, int32_t n)
 {
@@ -219,6 +276,8 @@ static int check_params(const orc_params* p)
         if (!(p->delta_ens >= 0.0) || !(p->ens_c >= 0.0) || !(p->ens_k > 0.0)) return -1;
         if ((p->limiter & ORC_LIM_ENS_RATIONAL) && !(p->ens_c > 0.0 && p->ens_k >= 0.5)) return -1;
     }
+    if (p->collision != ORC_COLL_LBGK && p->collision != ORC_COLL_ELBM) return -1;
+    if (p->collision == ORC_COLL_ELBM && p->qe != ORC_QE_ENTROPIC) return -1;
     if (p->bc == ORC_BC_CAVITY || p->bc == ORC_BC_CAVITY_DIFFUSIVE) {
         if (p->lattice != ORC_D2Q9 || p->nx < 4 || p->ny < 4) return -1;
     } else if (p->bc == ORC_BC_TUBE) {
@@ -477,8 +536,19 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
             s.n_fluid++;
             double ux = jx / rho, uy = jy / rho;   /* eq. (macro_dis) */
             orc_equilibrium(p->lattice, p->qe, rho, ux, uy, fs);
-            for (int i = 0; i < q; ++i)          /* eq. (collLBGK) */
-                fp[i] = fs[i] + c * (fs[i] - fl[i]);
+            if (p->collision == ORC_COLL_ELBM) {
+                /* eq. (elbmLB): f + alpha beta (f* - f) */
+                int32_t pr = 0;
+                const double alpha = orc_elbm_alpha(q, fl, fs, &pr);
+                for (int i = 0; i < q; ++i) fp[i] = fl[i] + alpha * p->beta * (fs[i] - fl[i]);
+                if (pr) {
+                    m[site] |= ORC_MASK_POSITIVITY;
+                    s.n_positivity++;
+                }
+            } else {
+                for (int i = 0; i < q; ++i)      /* eq. (collLBGK) */
+                    fp[i] = fs[i] + c * (fs[i] - fl[i]);
+            }
             dpre[site] = orc_delta_s(q, p->ds_form, fl, fs);
             dpost[site] = orc_delta_s(q, p->ds_form, fp, fs);
             for (int i = 0; i < q; ++i) {
@@ -607,6 +677,25 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                     m[site] |= ORC_MASK_ENSEMBLE;
                     s.n_ensemble++;
                     if (pe < phi) phi = pe;
+                }
+            }
+            if (p->limiter & ORC_LIM_POSITIVITY) {
+                /* positivity rule (Sec. 2.1): a post-collision state with a
+                 * negative population goes to the closest non-negative state
+                 * on the line through it and f*, where the first population
+                 * reaches 0: phi = min f*_i / (f*_i - f'_i) over f'_i < 0 */
+                double pp = 1.0;
+                for (int i = 0; i < q; ++i) {
+                    const double a = fpost[i * n + site], b = fst[i * n + site];
+                    if (a < 0.0) {
+                        const double v = b / (b - a);
+                        if (v < pp) pp = v;
+                    }
+                }
+                if (pp < 1.0) {
+                    m[site] |= ORC_MASK_POSITIVITY;
+                    s.n_positivity++;
+                    if (pp < phi) phi = pp;
                 }
             }
             double fs[9], fl[9];

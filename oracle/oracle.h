@@ -45,7 +45,9 @@ enum { ORC_DS_EXACT = 0, ORC_DS_QUADRATIC = 1 };
  * with a = delta / E^k (eq. smooth1), the rational phi of eq. (phiExamp),
  * and the entropy-budget threshold of eq. (EntThresh) */
 enum { ORC_LIM_TRIM = 1, ORC_LIM_MEDIAN = 2, ORC_LIM_ENS_THRESHOLD = 4, ORC_LIM_ENS_SMOOTH = 8,
-       ORC_LIM_ENS_RATIONAL = 16, ORC_LIM_ENS_BUDGET = 32 };
+       ORC_LIM_ENS_RATIONAL = 16, ORC_LIM_ENS_BUDGET = 32, ORC_LIM_POSITIVITY = 64 };
+/* collision: LBGK (eq. collLBGK) or ELBM (eq. elbm, entropic f* only) */
+enum { ORC_COLL_LBGK = 0, ORC_COLL_ELBM = 1 };
 enum { ORC_TRIM_HOMOTHETY = 0, ORC_TRIM_EHRENFEST = 1 };
 enum { ORC_MED_FLOOR = 0, ORC_MED_GATE = 1 };
 /* boundaries: periodic; lid-driven cavity with on-node bounce-back walls and
@@ -55,7 +57,7 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_CAVITY = 1, ORC_BC_TUBE = 2, ORC_BC_CAVITY_DI
 
 /* mask bits written per node by orc_step */
 enum { ORC_MASK_TRIM = 1, ORC_MASK_MEDIAN = 2, ORC_MASK_NONPOS = 4,
-       ORC_MASK_NOTFLUID = 8, ORC_MASK_ENSEMBLE = 16 };
+       ORC_MASK_NOTFLUID = 8, ORC_MASK_ENSEMBLE = 16, ORC_MASK_POSITIVITY = 32 };
 
 typedef struct {
     int32_t lattice, nx, ny;
@@ -69,6 +71,7 @@ typedef struct {
      * (smooth1) and (phiExamp); delta_ens the floor delta of the thresholds
      * and the delta of a = delta / E^k */
     double ens_c, ens_k, delta_ens;
+    int32_t collision;      /* ORC_COLL_LBGK or ORC_COLL_ELBM */
 } orc_params;
 
 typedef struct {
@@ -79,6 +82,7 @@ typedef struct {
     int64_t n_ensemble;     /* nodes an ensemble limiter moved (phi < 1) */
     double mean_dS;         /* E(Delta S'): sum_dS_post / n_fluid */
     double ens_threshold;   /* Delta S_t of the budget limiter, else of the threshold limiter, else 0 */
+    int64_t n_positivity;   /* nodes where the positivity rule acted (limiter, or ELBM without a root) */
 } orc_stats;
 
 int    orc_q(int32_t lattice);
@@ -93,6 +97,9 @@ double orc_delta_s(int32_t q, int32_t form, const double* f,
                    const double* fstar);
 /* h(x) = (1+x) ln(1+x) - x, the per-population entropy kernel */
 double orc_h(double x);
+/* alpha of the ELBM step for f with entropic f* (Q entries each); sets
+ * *posrule when the equation has no root short of the positivity boundary */
+double orc_elbm_alpha(int32_t q, const double* f, const double* fstar, int32_t* posrule);
 /* S(f) = -sum f_i ln(f_i / W_i) with the paper's W */
 double orc_entropy(int32_t lattice, const double* f);
 double orc_median(const double* v, int32_t n);

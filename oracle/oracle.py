@@ -25,7 +25,9 @@ LIM_ENS_THRESHOLD, LIM_ENS_SMOOTH, LIM_ENS_RATIONAL, LIM_ENS_BUDGET = 4, 8, 16, 
 TRIM_HOMOTHETY, TRIM_EHRENFEST = 0, 1
 MED_FLOOR, MED_GATE = 0, 1
 BC_PERIODIC, BC_CAVITY, BC_TUBE, BC_CAVITY_DIFFUSIVE = 0, 1, 2, 3
-MASK_TRIM, MASK_MEDIAN, MASK_NONPOS, MASK_NOTFLUID, MASK_ENSEMBLE = 1, 2, 4, 8, 16
+MASK_TRIM, MASK_MEDIAN, MASK_NONPOS, MASK_NOTFLUID, MASK_ENSEMBLE, MASK_POSITIVITY = 1, 2, 4, 8, 16, 32
+LIM_POSITIVITY = 64
+COLL_LBGK, COLL_ELBM = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -38,6 +40,7 @@ class Params(ctypes.Structure):
         ("rho0", ctypes.c_double), ("lid_ux", ctypes.c_double),
         ("entropy", ctypes.c_int32),
         ("ens_c", ctypes.c_double), ("ens_k", ctypes.c_double), ("delta_ens", ctypes.c_double),
+        ("collision", ctypes.c_int32),
     ]
 
 
@@ -50,6 +53,7 @@ class Stats(ctypes.Structure):
         ("n_trimmed", ctypes.c_int64), ("n_filtered", ctypes.c_int64),
         ("n_nonpositive", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
         ("n_ensemble", ctypes.c_int64), ("mean_dS", ctypes.c_double), ("ens_threshold", ctypes.c_double),
+        ("n_positivity", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -86,6 +90,8 @@ def lib():
         L.orc_entropy.restype = ctypes.c_double
         L.orc_median.argtypes = [dp, ctypes.c_int32]
         L.orc_median.restype = ctypes.c_double
+        L.orc_elbm_alpha.argtypes = [ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_elbm_alpha.restype = ctypes.c_double
         L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Stats),
                                ctypes.POINTER(ctypes.c_uint8), dp, dp]
         L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
@@ -139,6 +145,15 @@ def entropy(lattice: int, f: np.ndarray) -> float:
     return lib().orc_entropy(lattice, _dp(f))
 
 
+def elbm_alpha(f, fstar):
+    """alpha of the ELBM step and whether the positivity rule replaced the root"""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    fs = np.ascontiguousarray(fstar, dtype=np.float64)
+    pr = ctypes.c_int32()
+    a = lib().orc_elbm_alpha(len(f), _dp(f), _dp(fs), ctypes.byref(pr))
+    return a, bool(pr.value)
+
+
 def median(v) -> float:
     v = np.ascontiguousarray(v, dtype=np.float64)
     return lib().orc_median(_dp(v), len(v))
@@ -147,11 +162,12 @@ def median(v) -> float:
 def make_params(lattice=D2Q9, nx=8, ny=8, beta=0.9, qe=QE_POLY, ds_form=DS_EXACT, limiter=0,
                 trim_mode=TRIM_HOMOTHETY, median_mode=MED_FLOOR, bc=BC_PERIODIC, delta_trim=1e-3,
                 delta_median=1e-3, rho0=1.0, lid_ux=0.0, entropy=False, ens_c=0.0, ens_k=0.5,
-                delta_ens=0.0) -> Params:
+                delta_ens=0.0, collision=0) -> Params:
     if lattice == D1Q3:
         ny = 1
     return Params(lattice, nx, ny, beta, qe, ds_form, limiter, trim_mode, median_mode, bc,
-                  delta_trim, delta_median, rho0, lid_ux, 1 if entropy else 0, ens_c, ens_k, delta_ens)
+                  delta_trim, delta_median, rho0, lid_ux, 1 if entropy else 0, ens_c, ens_k, delta_ens,
+                  collision)
 
 
 def init_equilibrium(p: Params, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
