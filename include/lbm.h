@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 
 #if defined(__GNUC__)
 #define LBM_API __attribute__((visibility("default")))
@@ -82,7 +82,19 @@ enum lbm_qe { LBM_QE_POLYNOMIAL = 0, LBM_QE_ENTROPIC = 1 };
  *                  budget beyond sum Delta S puts it at 0
  * When several are on, phi is the smallest of their factors. */
 enum lbm_limiter { LBM_LIM_NONE = 0, LBM_LIM_TRIM = 1, LBM_LIM_MEDIAN = 2, LBM_LIM_ENS_THRESHOLD = 4,
-                   LBM_LIM_ENS_SMOOTH = 8, LBM_LIM_ENS_RATIONAL = 16, LBM_LIM_ENS_BUDGET = 32 };
+                   LBM_LIM_ENS_SMOOTH = 8, LBM_LIM_ENS_RATIONAL = 16, LBM_LIM_ENS_BUDGET = 32,
+                   LBM_LIM_POSITIVITY = 64 };
+/* LBM_LIM_POSITIVITY, the positivity rule (Sec. 2.1): a post-collision state
+ * with a negative population is moved to the closest non-negative state on
+ * the line through it and f*, phi = min f*_i / (f*_i - f'_i) over f'_i < 0.
+ * On D2Q9 it combines with the median or ensemble limiters only with the
+ * exact Delta S (LBM_EINVAL otherwise). */
+/* collision: LBGK (eq. collLBGK), or ELBM (eqs. elbm, elbmLB): f' = f +
+ * alpha beta (f* - f), alpha the nontrivial root of S((1 - alpha) f +
+ * alpha f*) = S(f), found per node to full precision, never lowering the
+ * entropy; when no such state is non-negative, the positivity rule (alpha at
+ * the positivity boundary).  ELBM needs LBM_QE_ENTROPIC. */
+enum lbm_collision { LBM_COLL_LBGK = 0, LBM_COLL_ELBM = 1 };
 /* trimming: homothety to Delta S_t = delta (eq. entrHom) or Ehrenfests' step
  * f -> f* (Sec. 3.2) at sites with Delta S > delta */
 enum lbm_trimmode { LBM_TRIM_HOMOTHETY = 0, LBM_TRIM_EHRENFEST = 1 };
@@ -112,6 +124,7 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT =
 #define LBM_MASK_NONPOS 4u   /* a population or f* was <= 0 (Delta S = +inf) */
 #define LBM_MASK_NOTFLUID 8u /* wall or lid node: no collision, no limiter */
 #define LBM_MASK_ENSEMBLE 16u /* an ensemble-dependent limiter moved the node (phi < 1) */
+#define LBM_MASK_POSITIVITY 32u /* the positivity rule acted (limiter, or ELBM without a root) */
 
 /* run flags */
 #define LBM_RUN_RECORD 1u    /* keep per-node mask and Delta S' of every step */
@@ -145,6 +158,7 @@ typedef struct {
                                    the rational phi, delta_0 of the budget; >= 0 */
     double ens_k;               /* exponent k of the smooth (> 0) and rational (>= 1/2) phi */
     double delta_ens;           /* floor delta of the thresholds; delta of a = delta / E^k */
+    int32_t collision;          /* enum lbm_collision; same in every domain of a context */
 } lbm_domain_desc;
 
 typedef struct {
@@ -179,6 +193,7 @@ typedef struct {
     int64_t n_trimmed, n_filtered, n_nonpositive, n_nonfinite, n_fluid;
     int64_t n_ensemble;         /* nodes an ensemble-dependent limiter moved */
     double ens_threshold;       /* Delta S_t of ENS_BUDGET, else of ENS_THRESHOLD (0 if off) */
+    int64_t n_positivity;       /* nodes the positivity rule moved (limiter, or ELBM without a root) */
 } lbm_entropy_stats_t;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -82,6 +82,7 @@ struct lbm_ctx {
     bool median_pass = false;   // D2Q9 with the median filter in some domain
     bool ens_pass = false;      // an ensemble-dependent limiter in some domain
     bool budget = false;        // the budget threshold in some domain
+    bool elbm = false;          // ELBM collisions (all domains)
     long long steps_done = 0, finalized_for = -1;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -133,11 +134,23 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
         const std::string where = "domain " + std::to_string(k) + ": ";
         if (d.struct_size < sizeof(lbm_domain_desc)) return fail(nullptr, LBM_EINVAL, where + "struct_size too small");
         if (d.lattice != LBM_D1Q3 && d.lattice != LBM_D2Q9) return fail(nullptr, LBM_EINVAL, where + "bad lattice");
-        if (d.lattice != d0.lattice || d.qe != d0.qe || d.ds_form != d0.ds_form || d.bc != d0.bc)
-            return fail(nullptr, LBM_EINVAL, where + "lattice, qe, ds_form and bc must match across domains");
+        if (d.lattice != d0.lattice || d.qe != d0.qe || d.ds_form != d0.ds_form || d.bc != d0.bc ||
+            d.collision != d0.collision)
+            return fail(nullptr, LBM_EINVAL, where + "lattice, qe, ds_form, bc and collision must match across domains");
+        if (d.collision != LBM_COLL_LBGK && d.collision != LBM_COLL_ELBM)
+            return fail(nullptr, LBM_EINVAL, where + "bad collision");
+        if (d.collision == LBM_COLL_ELBM && d.qe != LBM_QE_ENTROPIC)
+            return fail(nullptr, LBM_EINVAL, where + "ELBM needs the entropic f*");
         if (d.qe != LBM_QE_POLYNOMIAL && d.qe != LBM_QE_ENTROPIC) return fail(nullptr, LBM_EINVAL, where + "bad qe");
         if (d.ds_form != LBM_DS_EXACT && d.ds_form != LBM_DS_QUADRATIC) return fail(nullptr, LBM_EINVAL, where + "bad ds_form");
-        if (d.limiter < 0 || d.limiter > 63) return fail(nullptr, LBM_EINVAL, where + "bad limiter mask");
+        if (d.limiter < 0 || d.limiter > 127) return fail(nullptr, LBM_EINVAL, where + "bad limiter mask");
+        // a second pass rebuilds the applied factor from Delta S' alone, which
+        // the positivity factor is not; with the exact Delta S a node it acts
+        // on has Delta S' = +inf, and every second-pass limiter sends it to f*
+        if (d.lattice == LBM_D2Q9 && (d.limiter & LBM_LIM_POSITIVITY) &&
+            (d.limiter & (LBM_LIM_MEDIAN | kLimEns)) && d.ds_form != LBM_DS_EXACT)
+            return fail(nullptr, LBM_EINVAL,
+                        where + "the positivity rule with the median or ensemble limiters needs the exact Delta S");
         if (d.limiter & kLimEns) {
             if (!(d.ens_c >= 0.0) || !finite(d.ens_c) || !(d.ens_k > 0.0) || !finite(d.ens_k) ||
                 !(d.delta_ens >= 0.0) || !finite(d.delta_ens))
@@ -358,6 +371,7 @@ int upload_domains(lbm_ctx* ctx)
         d.ens_k = h.d.ens_k;
         d.delta_ens = h.d.delta_ens;
         d.diffusive = h.d.bc == LBM_BC_CAVITY_DIFFUSIVE ? 1 : 0;
+        d.collision = h.d.collision;
         const bool budget = h.d.limiter & kLimEnsBudget;
         d.bstate = budget ? reinterpret_cast<BudgetState*>(ctx->ws + h.off_bstate) : nullptr;
         d.bhist = budget ? reinterpret_cast<BudgetBucket*>(ctx->ws + h.off_bhist) : nullptr;
@@ -410,9 +424,9 @@ int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
     if (ev) e = hipEventRecord(ev[0], ctx->stream);
     if (e == hipSuccess) {
         if (ctx->lattice == LBM_D2Q9)
-            e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 0, ctx->stream);
+            e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->elbm ? 2 : 0, ctx->stream);
         else
-            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 0, ctx->stream);
+            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->elbm ? 2 : 0, ctx->stream);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
     // ensemble limiters: E(Delta S') of this step first (Sec. 3.3, 3.4)
@@ -523,6 +537,7 @@ int read_stats(lbm_ctx* ctx, int32_t d, lbm_entropy_stats_t* out)
     s.n_nonpositive = (int64_t)raw[kSNonpos];
     s.n_nonfinite = (int64_t)raw[kSNonfin];
     s.n_ensemble = (int64_t)raw[kSEns];
+    s.n_positivity = (int64_t)raw[kSPos];
     if (h.d.limiter & (LBM_LIM_ENS_THRESHOLD | LBM_LIM_ENS_BUDGET)) {
         double ev[kNEns] = {0, 0, 0, 0};
         if (ctx->steps_done > 0) {
@@ -601,6 +616,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     ctx->ds = domains[0].ds_form;
     // both cavity kinds run the cavity kernels; the wall rule is per domain
     ctx->bc = is_cavity(domains[0].bc) ? kCavity : domains[0].bc;
+    ctx->elbm = domains[0].collision == LBM_COLL_ELBM;
     ctx->flags = run->flags;
     ctx->stats_every = run->stats_every;
     ctx->probe_cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;

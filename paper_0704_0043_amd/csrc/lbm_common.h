@@ -11,16 +11,17 @@ enum { kPoly = 0, kEntropic = 1 };
 enum { kExact = 0, kQuad = 1 };
 enum { kPeriodic = 0, kCavity = 1, kTube = 2 };
 enum { kLimTrim = 1, kLimMedian = 2, kLimEnsThresh = 4, kLimEnsSmooth = 8, kLimEnsRational = 16,
-       kLimEnsBudget = 32, kLimEns = 4 | 8 | 16 | 32 };
+       kLimEnsBudget = 32, kLimEns = 4 | 8 | 16 | 32, kLimPos = 64 };
+enum { kLBGK = 0, kELBM = 1 };
 enum { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
-enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8, kMaskEns = 16 };
+enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8, kMaskEns = 16, kMaskPos = 32 };
 enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2 };
 
 constexpr int kThreads = 256;      // workgroup size of the step kernels (= D2Q9 tile width)
 constexpr int kWave = 64;          // wavefront size (CDNA)
 constexpr int kMaxTileH = 64;      // rows per D2Q9 tile
-constexpr int kNStat = 15;         // FP64 values per tile partial
+constexpr int kNStat = 16;         // FP64 values per tile partial
 
 // partial / stats slot layout (FP64 each)
 enum {
@@ -30,7 +31,8 @@ enum {
     kSTrim, kSFilt, kSNonpos, kSNonfin, kSFluid,
     kSAbove,      // median candidates (Delta S' > delta_median); in a collision partial: bit w set
                   // when wave w of the segment holds one (that wave stored its Delta S')
-    kSEns         // nodes an ensemble-dependent limiter moved
+    kSEns,        // nodes an ensemble-dependent limiter moved
+    kSPos         // nodes the positivity rule moved (limiter, or ELBM without a root)
 };
 
 // per-domain ensemble values of the current step (device array of kNEns doubles)
@@ -77,6 +79,7 @@ struct DomainDev {
     double rho0, lid_ux;
     int limiter, trim_mode, median_mode;
     int diffusive;          // cavity walls: 0 on-node bounce-back + equilibrium lid, 1 diffusive Maxwell
+    int collision;          // kLBGK or kELBM
     int probe_x, probe_y, probe_cap;
     float* probe;           // [probe_cap][2]
     unsigned char* mask;    // [ny*nx] when recording
@@ -135,9 +138,10 @@ struct StepArgs {
 };
 
 // Launchers (one per storage type / lattice), defined in the .hip files.
-// kernel 0: collision kernel; kernel 1: median filter and tile reduction (after kernel 0)
+// kernel 0: collision kernel (LBGK); kernel 2: the same with the ELBM collision;
+// kernel 1: the second pass (median filter, ensemble factors; after kernel 0 or 2)
 hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
-// kernel 0: D1Q3 step; kernel 1: D1Q3 ensemble pass
+// kernel 0: D1Q3 step (LBGK); kernel 2: the same with ELBM; kernel 1: D1Q3 ensemble pass
 hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
 // E(Delta S') and ensemble thresholds of the step just run (before the second pass)
 hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s);

@@ -248,6 +248,8 @@ struct SiteState {
     A gs[Q];      // shifted equilibrium g*_i = f*_i - w_i shift
     A d[Q];       // nonequilibrium part g_i - g*_i = f_i - f*_i
     A dpost;      // Delta S(f'), +inf when undefined
+    A c;          // f' - f* = -c d: 2 beta - 1 (LBGK), alpha beta - 1 (ELBM)
+    bool posrule; // ELBM: no root short of the positivity boundary
 };
 
 struct SiteScalars {
@@ -303,7 +305,71 @@ __device__ __forceinline__ void moments_equilibrium(const A (&g)[Lat<LAT>::Q], A
     for (int i = 0; i < Q; ++i) gs[i] = A(L::w(i)) * (dr + E[i]);
 }
 
-template <int LAT, int QE, int DS, class A>
+// h with its limit h(-1) = 1 (a population at exactly zero)
+template <class A>
+__device__ __forceinline__ A h_closed(A y)
+{
+    return y <= A(-1) ? A(1) : hkern(y);
+}
+
+// ELBM (eqs. elbm, entropy_estimate): alpha, the nontrivial root of
+// S(f~) = S(f) for f~ = (1 - alpha) f + alpha f*.  With the entropic f*,
+// S(f*) - S(g) = sum f*_i h(x_i(g)) on the line through f and f*, and f~ has
+// the deviation (1 - alpha) x, so in s = alpha - 1 the equation is
+// G(s) = sum f*_i h(-s x_i) - sum f*_i h(x_i) = 0 with G convex and
+// increasing on [0, s_max], s_max the positivity boundary of f~.  Newton from
+// the LBGK mirror s = 1, kept inside the bracket (bisection when a step
+// leaves it); the result is moved down to a point with G <= 0, so the
+// entropy does not decrease.  No root short of s_max (or a state f without
+// entropy): the positivity rule, s = s_max.
+template <int Q, class A>
+__device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
+{
+    constexpr A eps = sizeof(A) == 8 ? A(2.220446049250313e-16) : A(1.1920929e-7);
+    const A inf = A(__builtin_huge_val());
+    A smax = inf, target = A(0);
+    bool nonpos = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (x[i] > A(0)) smax = fmin(smax, A(1) / x[i]);
+        nonpos |= x[i] <= A(-1);
+        target += fs[i] * h_closed(x[i]);
+    }
+    posrule = false;
+    if (!(smax < inf)) return A(2);        // f = f*: every alpha gives f
+    auto G = [&](A s) {
+        A g = -target;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g += fs[i] * h_closed(-s * x[i]);
+        return g;
+    };
+    if (nonpos || G(smax) < A(0)) {
+        posrule = true;
+        return A(1) + smax;
+    }
+    A lo = A(0), hi = smax, s = fmin(A(1), A(0.5) * smax);
+    for (int it = 0; it < 60; ++it) {
+        A g = -target, dg = A(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const A y = -s * x[i];
+            g += fs[i] * h_closed(y);
+            dg -= fs[i] * x[i] * log1p(fmax(y, A(-1)));
+        }
+        if (g <= A(0)) lo = s;
+        else hi = s;
+        A sn = s - g / dg;
+        if (!(sn > lo && sn < hi)) sn = A(0.5) * (lo + hi);
+        const bool done = fabs(sn - s) <= A(2) * eps * s;
+        s = sn;
+        if (done) break;
+    }
+    for (int k = 0; k < 4 && G(s) > A(0); ++k) s *= A(1) - A(2) * eps;
+    if (G(s) > A(0)) s = lo;
+    return A(1) + s;
+}
+
+template <int LAT, int QE, int DS, bool ELBM = false, class A>
 __device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift, A c, SiteState<LAT, A>& o,
                                     SiteScalars& sc, bool want_pre)
 {
@@ -319,8 +385,20 @@ __device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift,
         o.d[i] = g[i] - o.gs[i];
         fs_ok &= fs[i] > A(0);
         pre_ok &= (g[i] + A(L::w(i)) * shift) > A(0);
-        post_ok &= (fs[i] - c * o.d[i]) > A(0);
     }
+    o.posrule = false;
+    if constexpr (ELBM) {
+        // eq. (elbmLB): f' = f + alpha beta (f* - f) = f* - (alpha beta - 1) d,
+        // beta = (c + 1) / 2
+        A xe[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) xe[i] = o.d[i] / fs[i];
+        const A alpha = elbm_alpha<Q>(fs, xe, o.posrule);
+        c = alpha * (A(0.5) * (c + A(1))) - A(1);
+    }
+    o.c = c;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) post_ok &= (fs[i] - c * o.d[i]) > A(0);
     A dpre = 0, dpost = 0;
     if constexpr (DS == kQuad) {
         // sum (f - f*)^2 / (2 f*); after collision f' - f* = -c d (eq. collLBGK)
@@ -356,6 +434,22 @@ __device__ __forceinline__ void collide_site(const A (&g)[Lat<LAT>::Q], A shift,
     sc.jy = double(jy);
     sc.ux = float(ux);
     sc.uy = float(uy);
+}
+
+// positivity rule (Sec. 2.1): the largest phi with f* + phi (f' - f*) >= 0,
+// min f*_i / (f*_i - f'_i) over the populations with f'_i < 0; 1 when none
+template <int LAT, class A>
+__device__ __forceinline__ A positivity_phi(const SiteState<LAT, A>& o, A shift)
+{
+    using L = Lat<LAT>;
+    A pp = A(1);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const A fs = A(L::w(i)) * shift + o.gs[i];
+        const A fp = fs - o.c * o.d[i];
+        if (fp < A(0)) pp = fmin(pp, fs / (fs - fp));
+    }
+    return pp;
 }
 
 // Delta S of f* + s (f' - f*) = f* - s c d, used for the limiter's entropy
@@ -434,7 +528,7 @@ __device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const Dom
 template <class S>
 struct AccT {
     S mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
-    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0, above = 0, ens = 0;
+    int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0, above = 0, ens = 0, pos = 0;
 
     __device__ void moments(const SiteScalars& s)
     {
@@ -466,7 +560,7 @@ __device__ inline void store_partial(const AccT<S>& acc, double* out, double* ld
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
                         double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above),
-                        double(acc.ens)};
+                        double(acc.ens), double(acc.pos)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -507,7 +601,7 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
                         double(acc.nonpos), double(acc.nonfin), double(acc.fluid), double(acc.above),
-                        double(acc.ens)};
+                        double(acc.ens), double(acc.pos)};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -563,15 +657,15 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
     const int wave = tid >> 6, lane = tid & 63;
     // kSAbove is not a count here: bit w is set when wave w holds a node above
     // the median tolerance (the median pass reads which waves stored Delta S')
-    const double cnt[7] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
+    const double cnt[8] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
                            double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
                            double(__popcll(__ballot(acc.fluid != 0))), __ballot(acc.above != 0) ? double(1 << wave) : 0.0,
-                           double(__popcll(__ballot(acc.ens != 0)))};
+                           double(__popcll(__ballot(acc.ens != 0))), double(__popcll(__ballot(acc.pos != 0)))};
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
+        for (int k = 0; k < 8; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
     }
     __syncthreads();
     if (tid < kNStat) {

@@ -190,7 +190,7 @@ __device__ __forceinline__ void diffusive_wall(gptr<T> dst, long long plane, lon
     }
 }
 
-template <class T, int QE, int DS, int BC>
+template <class T, int QE, int DS, int BC, bool ELBM = false>
 __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
 {
     using A = typename Store<T>::A;
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
             if (cls == kNodeFluid) {
                 SiteState<kD2Q9, A> S;
                 SiteScalars sc;
-                collide_site<kD2Q9, QE, DS>(g, shift, c, S, sc, true);
+                collide_site<kD2Q9, QE, DS, ELBM>(g, shift, c, S, sc, true);
                 acc.moments(sc);
                 acc.fluid_site(sc, S.dpost);
                 if (want_ent) {
@@ -248,18 +248,28 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                     p[1] = sc.uy;
                 }
                 unsigned mask = 0;
-                const A phi = trim_phi(D, S.dpost, mask);
-                store_limited<T>(dst, plane, row, cl.own, S, phi, c);
+                A phi = trim_phi(D, S.dpost, mask);
+                if (S.posrule) {
+                    mask |= kMaskPos;
+                    ++acc.pos;
+                }
+                if (D.limiter & kLimPos) {
+                    const A pp = positivity_phi<kD2Q9>(S, shift);
+                    if (pp < A(1)) {
+                        mask |= kMaskPos;
+                        ++acc.pos;
+                        phi = fmin(phi, pp);
+                    }
+                }
+                store_limited<T>(dst, plane, row, cl.own, S, phi, S.c);
                 if (keep_ds) {
                     // NaN counts as above: such a wave always stores its values
                     const bool up = (D.limiter & kLimMedian) && !(S.dpost <= A(D.delta_median));
                     if (up) acc.above = 1;
                     if (every || __ballot(up) != 0) Store<A>::st(dsb + node, S.dpost);
                 }
-                if (mask & kMaskTrim) {
-                    ++acc.trim;
-                    if (isfinite(S.dpost)) acc.lim += S.dpost - delta_s_scaled<kD2Q9, DS>(S, shift, c, phi);
-                }
+                if (mask & kMaskTrim) ++acc.trim;
+                if (phi < A(1) && isfinite(S.dpost)) acc.lim += S.dpost - delta_s_scaled<kD2Q9, DS>(S, shift, S.c, phi);
                 if (sc.nonpos) mask |= kMaskNonpos;
                 if (record) {
                     to_global<unsigned char>(D.mask)[node] = (unsigned char)mask;
@@ -588,7 +598,7 @@ __device__ inline void gather1d(gptr<const T> src, long long plane, int nx, int 
     }
 }
 
-template <class T, int QE, int DS, int BC>
+template <class T, int QE, int DS, int BC, bool ELBM = false>
 __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
 {
     using A = typename Store<T>::A;
@@ -624,7 +634,7 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
     A dsv = A(0);
     if (inside) {
         gather1d<BC>(src, plane, nx, x, g);
-        collide_site<LAT, QE, DS>(g, shift, c, S, sc, owned);
+        collide_site<LAT, QE, DS, ELBM>(g, shift, c, S, sc, owned);
         dsv = S.dpost;
         if (owned) {
             acc.moments(sc);
@@ -646,13 +656,25 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
         unsigned mask = 0;
         const bool has_med = (D.limiter & kLimMedian) && (BC == kPeriodic || (x >= 1 && x <= nx - 2));
         const A med = has_med ? med3(ds[tid - 1], ds[tid], ds[tid + 1]) : A(0);
-        const A phi = limiter_phi(S.dpost, has_med, med, D, mask);
-        const A k = phi * c;
+        A phi = limiter_phi(S.dpost, has_med, med, D, mask);
+        if (S.posrule) {
+            mask |= kMaskPos;
+            ++acc.pos;
+        }
+        if (D.limiter & kLimPos) {
+            const A pp = positivity_phi<LAT>(S, shift);
+            if (pp < A(1)) {
+                mask |= kMaskPos;
+                ++acc.pos;
+                phi = fmin(phi, pp);
+            }
+        }
+        const A k = phi * S.c;
 #pragma unroll
         for (int i = 0; i < Q; ++i) Store<T>::st(dst + i * plane + x, S.gs[i] - k * S.d[i]);
         if (mask & kMaskTrim) ++acc.trim;
         if (mask & kMaskMedian) ++acc.filt;
-        if (phi < A(1) && isfinite(S.dpost)) acc.lim += double(S.dpost - delta_s_scaled<LAT, DS>(S, shift, c, phi));
+        if (phi < A(1) && isfinite(S.dpost)) acc.lim += double(S.dpost - delta_s_scaled<LAT, DS>(S, shift, S.c, phi));
         if (sc.nonpos) mask |= kMaskNonpos;
         if (a.flags & kFlagRecord) {
             to_global<unsigned char>(D.mask)[x] = (unsigned char)mask;
@@ -748,12 +770,27 @@ __global__ void __launch_bounds__(kThreads) k_ens1d(StepArgs a)
         default: return hipErrorInvalidValue;                                                          \
         }                                                                                              \
     } while (0)
+// ELBM needs the entropic f*: kernels for qe = 1 only
+#define LBM_CASE_E(KER, D_, B_, ...) \
+    case 100 + D_ * 10 + B_: hipLaunchKernelGGL((KER<StT, 1, D_, B_, true>), __VA_ARGS__); break;
+#define LBM_DISPATCH_ELBM(KER, B0, B1, ...)                                                            \
+    do {                                                                                               \
+        switch (qe * 100 + ds * 10 + bc) {                                                             \
+            LBM_CASE_E(KER, 0, B0, __VA_ARGS__)                                                        \
+            LBM_CASE_E(KER, 0, B1, __VA_ARGS__)                                                        \
+            LBM_CASE_E(KER, 1, B0, __VA_ARGS__)                                                        \
+            LBM_CASE_E(KER, 1, B1, __VA_ARGS__)                                                        \
+        default: return hipErrorInvalidValue;                                                          \
+        }                                                                                              \
+    } while (0)
 
 hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const StepArgs& a, int kernel,
                                              hipStream_t s)
 {
     if (kernel == 0)
         LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.nrows), dim3(kThreads), 0, s, a);
+    else if (kernel == 2)
+        LBM_DISPATCH_ELBM(k_collide2d, 0, 1, dim3(a.nrows), dim3(kThreads), 0, s, a);
     else if (a.ens_pass)
         LBM_DISPATCH(k_median_ens2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     else
@@ -766,6 +803,8 @@ hipError_t LBM_CAT(launch_step1d, LBM_SUFFIX)(int qe, int ds, int bc, const Step
 {
     if (kernel == 0)
         LBM_DISPATCH(k_step1d, 0, 2, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
+    else if (kernel == 2)
+        LBM_DISPATCH_ELBM(k_step1d, 0, 2, dim3(a.ntiles + 1), dim3(kThreads), 0, s, a);
     else
         LBM_DISPATCH(k_ens1d, 0, 2, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     return hipGetLastError();

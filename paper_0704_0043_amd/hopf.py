@@ -13,7 +13,9 @@ From the last 1 % of each signal:
     linearly in Re past it, so Re_c is where the least-squares line through
     the oscillating runs crosses E_u^2 = 0;
   * the dominant frequency: the largest peak of the amplitude spectrum of
-    u_sig - mean, in cycles per non-dimensional time unit.
+    u_sig - mean, in cycles per non-dimensional time unit;
+  * the energy of an earlier window of the same length (ending at 90 % of the
+    run), which shows whether the signal has settled.
 
 L is N (the length in Re = u0 N / nu); the signal is in lattice units.
 """
@@ -80,8 +82,11 @@ def run(L, re_values, n: int = 100, u0: float = 0.1, time_units: float = 5000.0,
     """Run the batch and analyse the probe signals; prints progress to `log`."""
     steps = int(round(time_units * n / u0))
     keep = max(2, int(round(tail * steps)))
+    # the probes hold the last 10 tails, so the energy of an earlier window
+    # (ending at 90 % of the run) shows whether the signal is still changing
+    cap = min(steps, 10 * keep)
     doms = hopf_domains(L, re_values, n, u0)
-    run_desc = L.Run(storage=storage, graph_chunk=100, probe_capacity=keep, tile_h=16,
+    run_desc = L.Run(storage=storage, graph_chunk=100, probe_capacity=cap, tile_h=16,
                      stream=stream if stream is not None else 0)
     t0 = time.perf_counter()
     out = {"n": n, "u0": u0, "time_units": time_units, "steps": steps, "signal_steps": keep,
@@ -95,9 +100,13 @@ def run(L, re_values, n: int = 100, u0: float = 0.1, time_units: float = 5000.0,
             done += k
             print(f"[hopf] {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=log, flush=True)
         wall = time.perf_counter() - t0
-        sig = [L.lbm_probe_trace(ctx, k, keep) for k in range(len(doms))]
+        full = [L.lbm_probe_trace(ctx, k, cap) for k in range(len(doms))]
+        sig = [s[-keep:] for s in full]
+        early = [s[:keep] for s in full] if cap >= 2 * keep else sig
         stats = [L.lbm_entropy_stats(ctx, k) for k in range(len(doms))]
     e = [energy(s[:, 0], n, u0) for s in sig]
+    out["E_u_earlier"] = [energy(s[:, 0], n, u0) for s in early]
+    out["earlier_window_end"] = 1.0 - (cap - keep) / steps
     e2 = [v * v for v in e]
     rec, slope, used = critical_reynolds(re_values, e2)
     out.update({

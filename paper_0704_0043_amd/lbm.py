@@ -29,12 +29,15 @@ LBM_D1Q3, LBM_D2Q9 = 1, 2
 LBM_QE_POLYNOMIAL, LBM_QE_ENTROPIC = 0, 1
 LBM_LIM_NONE, LBM_LIM_TRIM, LBM_LIM_MEDIAN = 0, 1, 2
 LBM_LIM_ENS_THRESHOLD, LBM_LIM_ENS_SMOOTH, LBM_LIM_ENS_RATIONAL, LBM_LIM_ENS_BUDGET = 4, 8, 16, 32
+LBM_LIM_POSITIVITY = 64
+LBM_COLL_LBGK, LBM_COLL_ELBM = 0, 1
 LBM_TRIM_HOMOTHETY, LBM_TRIM_EHRENFEST = 0, 1
 LBM_MED_FLOOR_DELTA, LBM_MED_GATE_DELTA = 0, 1
 LBM_DS_EXACT, LBM_DS_QUADRATIC = 0, 1
 LBM_BC_PERIODIC, LBM_BC_CAVITY, LBM_BC_TUBE_ENDS, LBM_BC_CAVITY_DIFFUSIVE = 0, 1, 2, 3
 LBM_F64, LBM_F32, LBM_F16_SHIFT, LBM_BF16_SHIFT = 0, 1, 2, 3
 LBM_MASK_TRIM, LBM_MASK_MEDIAN, LBM_MASK_NONPOS, LBM_MASK_NOTFLUID, LBM_MASK_ENSEMBLE = 1, 2, 4, 8, 16
+LBM_MASK_POSITIVITY = 32
 LBM_RUN_RECORD, LBM_RUN_ENTROPY, LBM_RUN_NO_GRAPH, LBM_RUN_NO_TUNE = 1, 2, 4, 8
 
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16_SHIFT: 2, LBM_BF16_SHIFT: 2}
@@ -53,6 +56,7 @@ class lbm_domain_desc(ctypes.Structure):
         ("rho_init", _dp), ("u_init", _dp), ("f_init", _dp),
         ("probe_x", ctypes.c_int32), ("probe_y", ctypes.c_int32),
         ("ens_c", ctypes.c_double), ("ens_k", ctypes.c_double), ("delta_ens", ctypes.c_double),
+        ("collision", ctypes.c_int32),
     ]
 
 
@@ -76,6 +80,7 @@ class lbm_entropy_stats_t(ctypes.Structure):
         ("n_trimmed", ctypes.c_int64), ("n_filtered", ctypes.c_int64), ("n_nonpositive", ctypes.c_int64),
         ("n_nonfinite", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
         ("n_ensemble", ctypes.c_int64), ("ens_threshold", ctypes.c_double),
+        ("n_positivity", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -165,6 +170,7 @@ class Domain:
     ens_c: float = 0.0
     ens_k: float = 0.5
     delta_ens: float = 0.0
+    collision: int = LBM_COLL_LBGK
     rho_init: np.ndarray | None = None
     u_init: np.ndarray | None = None
     f_init: np.ndarray | None = None
@@ -186,7 +192,7 @@ class Domain:
         d = lbm_domain_desc()
         d.struct_size = ctypes.sizeof(lbm_domain_desc)
         for k in ("lattice", "nx", "ny", "beta", "qe", "limiter", "trim_mode", "median_mode", "ds_form", "bc",
-                  "delta_trim", "delta_median", "rho0", "lid_ux", "ens_c", "ens_k", "delta_ens"):
+                  "delta_trim", "delta_median", "rho0", "lid_ux", "ens_c", "ens_k", "delta_ens", "collision"):
             setattr(d, k, getattr(self, k))
         self._keep = []
         for name, arr, size in (("rho_init", self.rho_init, n), ("u_init", self.u_init, self.dim * n),

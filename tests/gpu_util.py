@@ -31,7 +31,8 @@ def oracle_params(d, entropy=False):
     return o.make_params(lattice=d.lattice, nx=d.nx, ny=d.ny, beta=d.beta, qe=d.qe, ds_form=d.ds_form,
                          limiter=d.limiter, trim_mode=d.trim_mode, median_mode=d.median_mode, bc=d.bc,
                          delta_trim=d.delta_trim, delta_median=d.delta_median, rho0=d.rho0, lid_ux=d.lid_ux,
-                         entropy=entropy, ens_c=d.ens_c, ens_k=d.ens_k, delta_ens=d.delta_ens)
+                         entropy=entropy, ens_c=d.ens_c, ens_k=d.ens_k, delta_ens=d.delta_ens,
+                         collision=d.collision)
 
 
 def say(*a):
@@ -147,7 +148,8 @@ def assert_stats_close(pr, rtol=1e-11, counts=True, skip=()):
         assert g[k] == pytest.approx(o[k], rel=rtol, abs=1e-300), k
     assert abs(g["limiter_production"] - o["limiter_production"]) <= rtol * max(o["sum_dS_post"], 1e-300) * 10
     if counts:
-        for k in ("n_trimmed", "n_filtered", "n_nonpositive", "n_nonfinite", "n_fluid", "n_ensemble"):
+        for k in ("n_trimmed", "n_filtered", "n_nonpositive", "n_nonfinite", "n_fluid", "n_ensemble",
+                  "n_positivity"):
             if k in skip:
                 continue
             assert g[k] == o[k], (k, g[k], o[k])

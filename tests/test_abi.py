@@ -84,7 +84,7 @@ def test_struct_layouts_match_binding(L):
 
 
 def test_host_only_entry_points(L):
-    assert L.lbm_abi_version() == 2
+    assert L.lbm_abi_version() == 3
     assert L.lbm_beta_from_nu(1e-4) == pytest.approx(1 / (6e-4 + 1), rel=1e-15)
     assert "invalid" in L.lbm_strerror(L.LBM_EINVAL)
     n = L.lbm_workspace_bytes([L.Domain(nx=128, ny=64)], L.Run(storage=L.LBM_F32))
@@ -101,10 +101,11 @@ def test_host_only_entry_points(L):
 @pytest.mark.parametrize("bad", [
     dict(beta=1.5), dict(beta=-0.1), dict(delta_trim=-1.0), dict(delta_median=float("nan")),
     dict(nx=0), dict(bc=1, nx=3, ny=10), dict(lattice=3), dict(lattice=1, bc=1),
-    dict(lattice=2, bc=2), dict(qe=7), dict(limiter=64), dict(rho0=0.0), dict(probe=(500, 1)),
+    dict(lattice=2, bc=2), dict(qe=7), dict(rho0=0.0), dict(probe=(500, 1)),
     dict(limiter=8, ens_k=0.0), dict(limiter=16, ens_c=0.0), dict(limiter=4, delta_ens=-1.0),
     dict(limiter=16, ens_c=1.0, ens_k=0.25), dict(limiter=4, ens_c=float("inf")),
-    dict(bc=1, nx=10, ny=10, probe=(0, 5)),
+    dict(bc=1, nx=10, ny=10, probe=(0, 5)), dict(limiter=128), dict(collision=2), dict(collision=1, qe=0),
+    dict(limiter=64 | 2, ds_form=1), dict(bc=3, nx=3, ny=10), dict(lattice=1, bc=3),
 ])
 def test_invalid_descriptors_are_rejected_before_any_device_call(L, bad):
     kw = dict(nx=32, ny=16)
