@@ -200,6 +200,23 @@ def variants(torch, L, wl, stream, args):
                      "threshold": st["ens_threshold"], "mean_dS": st["mean_dS"], "steps": steps}
     res["ensemble_limiters_4096"] = ens
 
+    # ELBM collisions (a root solve per node: arithmetic-bound) on the
+    # headline grid without limiters, FP32 storage, against LBGK on the same
+    print("[bench] variant 4096^2 ELBM vs LBGK", file=sys.stderr, flush=True)
+    coll = {}
+    for name, cv in (("lbgk", L.LBM_COLL_LBGK), ("elbm", L.LBM_COLL_ELBM)):
+        dom = c2_domain(L, wl, 4096)
+        dom.qe, dom.limiter, dom.collision = L.LBM_QE_ENTROPIC, L.LBM_LIM_NONE, cv
+        with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
+            ms = time_steps(torch, L, ctx, stream, steps, 16)
+            st = L.lbm_entropy_stats(ctx)
+            k1, _ = L.lbm_kernel_times(ctx, 20)
+        sites = dom.nx * dom.ny
+        coll[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
+                      "collide_ms": round(k1, 5), "n_positivity": st["n_positivity"], "steps": steps}
+    coll["elbm"]["vs_lbgk"] = round(coll["elbm"]["mlups"] / coll["lbgk"]["mlups"], 3)
+    res["collision_4096_entropic"] = coll
+
     print("[bench] variant cavity ensemble (256 domains)", file=sys.stderr, flush=True)
     batch = wl.cavity_batch(256)
     doms = []
