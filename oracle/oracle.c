@@ -231,6 +231,25 @@ double orc_elbm_alpha(int32_t q, const double* f, const double* fstar, int32_t* 
     return 1.0 + lo;
 }
 
+/* Homothety toward f* down to Delta S = t (eq. entrHom): phi = sqrt(t / d),
+ * which reaches t exactly in the quadratic form; with p->homothety and the
+ * exact form, the root of Delta S(f* + phi (f' - f*)) = t (Sec. 3.6), by
+ * bisection on [0, 1] to 1e-15, taking the lower end (the limited state does
+ * not exceed t).  Delta S' = +inf gives 0. */
+static double homothety_phi(const orc_params* p, int q, const double* fpost, const double* fs, double d, double t)
+{
+    if (!isfinite(d)) return 0.0;
+    if (!p->homothety || p->ds_form == ORC_DS_QUADRATIC) return sqrt(t / d);
+    double lo = 0.0, hi = 1.0, g[9];
+    while (hi - lo > 1e-15) {
+        const double mid = 0.5 * (lo + hi);
+        for (int i = 0; i < q; ++i) g[i] = fs[i] + mid * (fpost[i] - fs[i]);
+        if (orc_delta_s(q, ORC_DS_EXACT, g, fs) <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 /* Sec. 3.5: sort the neighbourhood, take the middle value. */
 double orc_median(const double* v, int32_t n)
 {
@@ -277,6 +296,8 @@ static int check_params(const orc_params* p)
         if ((p->limiter & ORC_LIM_ENS_RATIONAL) && !(p->ens_c > 0.0 && p->ens_k >= 0.5)) return -1;
     }
     if (p->collision != ORC_COLL_LBGK && p->collision != ORC_COLL_ELBM) return -1;
+    if (p->homothety != 0 && p->homothety != 1) return -1;
+    if (p->top_k < 0) return -1;
     if (p->collision == ORC_COLL_ELBM && p->qe != ORC_QE_ENTROPIC) return -1;
     if (p->bc == ORC_BC_CAVITY || p->bc == ORC_BC_CAVITY_DIFFUSIVE) {
         if (p->lattice != ORC_D2Q9 || p->nx < 4 || p->ny < 4) return -1;
@@ -595,6 +616,24 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
         }
     }
 
+    /* top-k trimming (Sec. 3.2): the k-th largest finite Delta S' above
+     * delta; trimming then acts where Delta S' >= that value */
+    double topk_value = -INFINITY;
+    if ((p->limiter & ORC_LIM_TRIM) && p->top_k > 0) {
+        double* vals = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+        int mv = 0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double d = dpost[y * nx + x];
+                if (node_type(p, x, y) == NODE_FLUID && isfinite(d) && d > p->delta_trim) vals[mv++] = d;
+            }
+        if (mv > p->top_k) {
+            qsort(vals, (size_t)mv, sizeof(double), cmp_descending);
+            topk_value = vals[p->top_k - 1];
+        }
+        free(vals);
+    }
+
     /* pass 2: limiter on the post-collision state */
     double max_ds = 0.0;
     for (int y = 0; y < ny; ++y)
@@ -613,12 +652,19 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 if (d > max_ds) max_ds = d;
             }
             double phi = 1.0;
+            double fpn[9], fsn[9];              /* f' and f* of this node */
+            for (int i = 0; i < q; ++i) {
+                fpn[i] = fpost[i * n + site];
+                fsn[i] = fst[i * n + site];
+            }
             if (p->limiter & ORC_LIM_TRIM) {
                 /* eq. (entrHom) with Delta S_t = delta, or an Ehrenfests' step */
                 double t = p->delta_trim;
-                if (d > t) {
+                if (d > t && (isinf(d) || d >= topk_value)) {
                     m[site] |= ORC_MASK_TRIM;
-                    double pt = p->trim_mode == ORC_TRIM_EHRENFEST ? 0.0 : sqrt(t / d);
+                    double pt = p->trim_mode == ORC_TRIM_EHRENFEST
+                                    ? 0.0
+                                    : homothety_phi(p, q, fpn, fsn, d, t);
                     if (pt < phi) phi = pt;
                     s.n_trimmed++;
                 }
@@ -641,7 +687,7 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                     }
                     if (hit) {
                         m[site] |= ORC_MASK_MEDIAN;
-                        double pm = sqrt(t / d);
+                        double pm = homothety_phi(p, q, fpn, fsn, d, t);
                         if (pm < phi) phi = pm;
                         s.n_filtered++;
                     }
@@ -650,11 +696,11 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
             if (ens) {
                 double pe = 1.0;
                 if ((p->limiter & ORC_LIM_ENS_THRESHOLD) && d > t_thresh) {
-                    const double v = sqrt(t_thresh / d);    /* eq. (entrHom) */
+                    const double v = homothety_phi(p, q, fpn, fsn, d, t_thresh);   /* eq. (entrHom) */
                     if (v < pe) pe = v;
                 }
                 if ((p->limiter & ORC_LIM_ENS_BUDGET) && d > t_budget) {
-                    const double v = sqrt(t_budget / d);
+                    const double v = homothety_phi(p, q, fpn, fsn, d, t_budget);
                     if (v < pe) pe = v;
                 }
                 if ((p->limiter & ORC_LIM_ENS_SMOOTH) && mean_ds > 0.0 && d > 0.0) {

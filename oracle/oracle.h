@@ -72,6 +72,15 @@ typedef struct {
      * and the delta of a = delta / E^k */
     double ens_c, ens_k, delta_ens;
     int32_t collision;      /* ORC_COLL_LBGK or ORC_COLL_ELBM */
+    /* homothety to a threshold Delta S_t (trimming, median, threshold and
+     * budget limiters): 0: phi = sqrt(Delta S_t / Delta S') (eq. entrHom,
+     * exact in the quadratic form); 1: the root of
+     * Delta S(f* + phi (f' - f*)) = Delta S_t (Sec. 3.6, exact form) */
+    int32_t homothety;
+    /* trimming at most at the top_k nodes of largest finite Delta S' > delta
+     * (ties at the k-th value included; nodes with Delta S' = +inf always);
+     * 0: every node above delta (Sec. 3.2) */
+    int64_t top_k;
 } orc_params;
 
 typedef struct {

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("rho0", ctypes.c_double), ("lid_ux", ctypes.c_double),
         ("entropy", ctypes.c_int32),
         ("ens_c", ctypes.c_double), ("ens_k", ctypes.c_double), ("delta_ens", ctypes.c_double),
-        ("collision", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("homothety", ctypes.c_int32), ("top_k", ctypes.c_int64),
     ]
 
 
@@ -162,12 +162,12 @@ def median(v) -> float:
 def make_params(lattice=D2Q9, nx=8, ny=8, beta=0.9, qe=QE_POLY, ds_form=DS_EXACT, limiter=0,
                 trim_mode=TRIM_HOMOTHETY, median_mode=MED_FLOOR, bc=BC_PERIODIC, delta_trim=1e-3,
                 delta_median=1e-3, rho0=1.0, lid_ux=0.0, entropy=False, ens_c=0.0, ens_k=0.5,
-                delta_ens=0.0, collision=0) -> Params:
+                delta_ens=0.0, collision=0, homothety=0, top_k=0) -> Params:
     if lattice == D1Q3:
         ny = 1
     return Params(lattice, nx, ny, beta, qe, ds_form, limiter, trim_mode, median_mode, bc,
                   delta_trim, delta_median, rho0, lid_ux, 1 if entropy else 0, ens_c, ens_k, delta_ens,
-                  collision)
+                  collision, homothety, top_k)
 
 
 def init_equilibrium(p: Params, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
