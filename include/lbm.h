@@ -159,6 +159,15 @@ typedef struct {
     double ens_k;               /* exponent k of the smooth (> 0) and rational (>= 1/2) phi */
     double delta_ens;           /* floor delta of the thresholds; delta of a = delta / E^k */
     int32_t collision;          /* enum lbm_collision; same in every domain of a context */
+    int32_t homothety;          /* 0: a homothety to Delta S_t scales f' - f* by sqrt(Delta S_t /
+                                   Delta S') (eq. entrHom, exact in the quadratic form); 1: with
+                                   the exact Delta S, by the root phi of Delta S(f* + phi (f' -
+                                   f*)) = Delta S_t (Sec. 3.6); trimming, median, threshold and
+                                   budget limiters */
+    int64_t top_k;              /* > 0: trimming only at the top_k nodes of largest finite
+                                   Delta S' above delta_trim (Sec. 3.2; ties at the k-th value
+                                   included, Delta S' = +inf always), by a radix selection each
+                                   step; not with LBM_LIM_ENS_BUDGET; 0: every node above delta */
 } lbm_domain_desc;
 
 typedef struct {

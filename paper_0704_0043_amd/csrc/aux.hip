@@ -89,6 +89,19 @@ __global__ void __launch_bounds__(kThreads) k_ens_prepare(StepArgs a, int parity
             // no budget: the threshold sits at the largest value, nothing moves
             D.ens[kEBudget] = fmax(budget > 0.0 ? 0.0 : D.stats[kSMax], D.delta_ens);
         }
+        if (D.limiter & kLimTopK) {
+            // top-k trimming (Sec. 3.2): the k-th largest finite Delta S' by the
+            // same radix selection, counts only; -inf (every node above
+            // delta) until found
+            BudgetState& b = *D.bstate;
+            b.prefix = 0;
+            b.budget = double(D.top_k);
+            b.s_above = 0.0;
+            b.c_above = 0.0;
+            b.level = 0;
+            b.done = 0;
+            D.ens[kETopk] = -__builtin_huge_val();
+        }
     }
 }
 
@@ -143,7 +156,7 @@ __global__ void __launch_bounds__(kThreads) k_budget_hist(StepArgs a, int level)
     __shared__ unsigned hhi[kBudgetBuckets];
     const Tile t = a.tiles[blockIdx.x];
     const DomainDev& D = a.dom[t.domain];
-    if (!(D.limiter & kLimEnsBudget) || D.bstate->done) return;
+    if (!(D.limiter & (kLimEnsBudget | kLimTopK)) || D.bstate->done) return;
     const unsigned long long prefix = D.bstate->prefix;
     const int lo = budget_lo(K::dbl, level), hi = budget_hi(K::dbl, level);
     const U dmask = (U(1) << (hi - lo)) - 1;
@@ -302,6 +315,88 @@ __global__ void __launch_bounds__(kThreads) k_budget_select(StepArgs a, int leve
     }
 }
 
+// One level of the top-k selection, one workgroup per domain: the bucket
+// holding the k-th largest value is the highest one where the count of the
+// values at or above its lower edge reaches k.  At the last level the bucket
+// is a single value, the k-th largest; trimming acts at and above it (ties
+// included).  Fewer than k finite values: every node above delta.
+template <class A>
+__global__ void __launch_bounds__(kThreads) k_topk_select(StepArgs a, int level)
+{
+    using K = BKey<A>;
+    using U = typename K::U;
+    constexpr int per = kBudgetBuckets / kThreads;
+    __shared__ double tc[kThreads];
+    __shared__ int best;
+    const DomainDev& D = a.dom[blockIdx.x];
+    if (!(D.limiter & kLimTopK)) return;
+    BudgetState* bs = D.bstate;
+    if (bs->done) return;
+    const int tid = int(threadIdx.x);
+    const unsigned long long prefix = bs->prefix;
+    const int lo = budget_lo(K::dbl, level), hi = budget_hi(K::dbl, level);
+    const int w = hi - lo;
+    const int nb = 1 << w;
+    double c[per];
+    double my_c = 0.0;
+#pragma unroll
+    for (int i = per - 1; i >= 0; --i) {
+        BudgetBucket& gb = D.bhist[tid * per + i];
+        c[i] = double(gb.n);
+        gb.n = 0;
+        gb.lo = 0;
+        gb.hi = 0;
+        my_c += c[i];
+    }
+    tc[tid] = my_c;
+    if (tid == 0) best = -1;
+    __syncthreads();
+    if (tid == 0) {
+        double rc = bs->c_above;
+        for (int k = kThreads - 1; k >= 0; --k) {
+            const double v = tc[k];
+            tc[k] = rc;
+            rc += v;
+        }
+    }
+    __syncthreads();
+    const double kk = bs->budget;
+    double C = tc[tid], ca = 0.0, ca0 = 0.0;
+    int mine = -1;
+#pragma unroll
+    for (int i = per - 1; i >= 0; --i) {
+        const int b = tid * per + i;
+        if (i == 0) ca0 = C;
+        const double C1 = C + c[i];
+        if (mine < 0 && b < nb && C1 >= kk) {
+            mine = b;
+            ca = C;
+        }
+        C = C1;
+    }
+    if (mine >= 0) atomicMax(&best, mine);
+    __syncthreads();
+    int j = best;
+    if (j < 0 && level == 0) {
+        if (tid == 0) bs->done = 1;      // fewer than k values: no limit
+        return;
+    }
+    if (j < 0) {
+        j = 0;
+        mine = tid == 0 ? 0 : -1;
+        ca = ca0;
+    }
+    if (mine != j) return;
+    const U edge = U(((prefix << w) | (unsigned long long)j) << lo);
+    bs->prefix = (prefix << w) | (unsigned long long)j;
+    bs->c_above = ca;
+    bs->level = level + 1;
+    if (level + 1 == budget_levels(K::dbl)) {
+        D.ens[kETopk] = K::value(edge);
+        bs->done = 1;
+    }
+}
+
 hipError_t launch_budget(int storage, int bc, const StepArgs& a, hipStream_t s)
 {
     const bool dbl = storage == kF64;
@@ -312,12 +407,14 @@ hipError_t launch_budget(int storage, int bc, const StepArgs& a, hipStream_t s)
             else
                 hipLaunchKernelGGL((k_budget_hist<double, false>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
             hipLaunchKernelGGL(k_budget_select<double>, dim3(a.ndomains), dim3(kThreads), 0, s, a, level);
+            hipLaunchKernelGGL(k_topk_select<double>, dim3(a.ndomains), dim3(kThreads), 0, s, a, level);
         } else {
             if (bc == kCavity)
                 hipLaunchKernelGGL((k_budget_hist<float, true>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
             else
                 hipLaunchKernelGGL((k_budget_hist<float, false>), dim3(a.ntiles), dim3(kThreads), 0, s, a, level);
             hipLaunchKernelGGL(k_budget_select<float>, dim3(a.ndomains), dim3(kThreads), 0, s, a, level);
+            hipLaunchKernelGGL(k_topk_select<float>, dim3(a.ndomains), dim3(kThreads), 0, s, a, level);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -31,6 +31,16 @@ int strips_of(int nx) { return (nx + kThreads - 1) / kThreads; }
 
 bool is_cavity(int bc) { return bc == LBM_BC_CAVITY || bc == LBM_BC_CAVITY_DIFFUSIVE; }
 
+// trimming limited to the top_k largest Delta S' (a second-pass limiter)
+bool is_topk(const lbm_domain_desc& d) { return (d.limiter & LBM_LIM_TRIM) && d.top_k > 0; }
+// limiters that need the whole domain's Delta S' before any node is limited
+bool deferred(const lbm_domain_desc& d) { return (d.limiter & kLimEns) || is_topk(d); }
+// the device limiter mask: top-k trimming moves to the second pass
+int device_limiter(const lbm_domain_desc& d)
+{
+    return is_topk(d) ? ((d.limiter & ~kLimTrim) | kLimTopK) : d.limiter;
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int q_of(int lattice) { return lattice == LBM_D2Q9 ? 9 : 3; }
@@ -141,6 +151,10 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
             return fail(nullptr, LBM_EINVAL, where + "bad collision");
         if (d.collision == LBM_COLL_ELBM && d.qe != LBM_QE_ENTROPIC)
             return fail(nullptr, LBM_EINVAL, where + "ELBM needs the entropic f*");
+        if (d.homothety != 0 && d.homothety != 1) return fail(nullptr, LBM_EINVAL, where + "bad homothety");
+        if (d.top_k < 0) return fail(nullptr, LBM_EINVAL, where + "top_k must be >= 0");
+        if (d.top_k > 0 && (d.limiter & LBM_LIM_ENS_BUDGET))
+            return fail(nullptr, LBM_EINVAL, where + "top_k trimming and the budget threshold cannot share a domain");
         if (d.qe != LBM_QE_POLYNOMIAL && d.qe != LBM_QE_ENTROPIC) return fail(nullptr, LBM_EINVAL, where + "bad qe");
         if (d.ds_form != LBM_DS_EXACT && d.ds_form != LBM_DS_QUADRATIC) return fail(nullptr, LBM_EINVAL, where + "bad ds_form");
         if (d.limiter < 0 || d.limiter > 127) return fail(nullptr, LBM_EINVAL, where + "bad limiter mask");
@@ -245,7 +259,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         }
         h.off_stats = off;
         off = align_up(off + (kNStat + 1) * sizeof(double), kAlign);
-        const bool ens = h.d.limiter & kLimEns;
+        const bool ens = deferred(h.d);
         h.dsbuf = (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN)) || ens;
         if (h.dsbuf) {
             h.off_dsbuf = off;
@@ -258,7 +272,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         }
         h.off_ens = off;
         off = align_up(off + kNEns * sizeof(double), kAlign);
-        if (h.d.limiter & kLimEnsBudget) {
+        if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {
             h.off_bstate = off;
             off = align_up(off + sizeof(BudgetState), kAlign);
             h.off_bhist = off;
@@ -372,7 +386,10 @@ int upload_domains(lbm_ctx* ctx)
         d.delta_ens = h.d.delta_ens;
         d.diffusive = h.d.bc == LBM_BC_CAVITY_DIFFUSIVE ? 1 : 0;
         d.collision = h.d.collision;
-        const bool budget = h.d.limiter & kLimEnsBudget;
+        d.homothety = h.d.homothety;
+        d.top_k = h.d.top_k;
+        d.limiter = device_limiter(h.d);
+        const bool budget = (h.d.limiter & kLimEnsBudget) || is_topk(h.d);
         d.bstate = budget ? reinterpret_cast<BudgetState*>(ctx->ws + h.off_bstate) : nullptr;
         d.bhist = budget ? reinterpret_cast<BudgetBucket*>(ctx->ws + h.off_bhist) : nullptr;
     }
@@ -624,8 +641,8 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     plan(ctx->dom, domains, n_domains, run, ctx->lay);
     for (const auto& h : ctx->dom) {
         ctx->median_pass = ctx->median_pass || (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN));
-        ctx->ens_pass = ctx->ens_pass || (h.d.limiter & kLimEns);
-        ctx->budget = ctx->budget || (h.d.limiter & kLimEnsBudget);
+        ctx->ens_pass = ctx->ens_pass || deferred(h.d);
+        ctx->budget = ctx->budget || (h.d.limiter & kLimEnsBudget) || is_topk(h.d);
     }
 
     auto bail = [&](int code) {
@@ -659,7 +676,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
 
     // budget histograms start zero; every selection level leaves them zero
     for (const auto& h : ctx->dom)
-        if (h.d.limiter & kLimEnsBudget) {
+        if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {
             e = hipMemsetAsync(ctx->ws + h.off_bhist, 0, kBudgetBuckets * sizeof(BudgetBucket), ctx->stream);
             if (e != hipSuccess)
                 return bail(fail(nullptr, LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));

@@ -11,7 +11,10 @@ enum { kPoly = 0, kEntropic = 1 };
 enum { kExact = 0, kQuad = 1 };
 enum { kPeriodic = 0, kCavity = 1, kTube = 2 };
 enum { kLimTrim = 1, kLimMedian = 2, kLimEnsThresh = 4, kLimEnsSmooth = 8, kLimEnsRational = 16,
-       kLimEnsBudget = 32, kLimEns = 4 | 8 | 16 | 32, kLimPos = 64 };
+       kLimEnsBudget = 32, kLimPos = 64,
+       // internal: trimming limited to the top_k largest Delta S' (a second-pass
+       // limiter; the domain's kLimTrim bit is cleared on the device)
+       kLimTopK = 128, kLimEns = 4 | 8 | 16 | 32 | 128 };
 enum { kLBGK = 0, kELBM = 1 };
 enum { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
@@ -36,7 +39,7 @@ enum {
 };
 
 // per-domain ensemble values of the current step (device array of kNEns doubles)
-enum { kEMean = 0, kEThresh, kESmoothA, kEBudget, kNEns };
+enum { kEMean = 0, kEThresh, kESmoothA, kEBudget, kETopk, kNEns };
 
 // Entropy-budget threshold (eq. EntThresh) by radix selection over the bit
 // patterns of the non-negative Delta S' values, most significant digit
@@ -80,6 +83,8 @@ struct DomainDev {
     int limiter, trim_mode, median_mode;
     int diffusive;          // cavity walls: 0 on-node bounce-back + equilibrium lid, 1 diffusive Maxwell
     int collision;          // kLBGK or kELBM
+    int homothety;          // 1: homothety targets reached exactly with the exact Delta S
+    long long top_k;        // kLimTopK: trimming at the top_k largest finite Delta S' only
     int probe_x, probe_y, probe_cap;
     float* probe;           // [probe_cap][2]
     unsigned char* mask;    // [ny*nx] when recording

@@ -490,15 +490,17 @@ __device__ inline double entropy_site(const A (&g)[Lat<LAT>::Q], A shift)
 // phi for one fluid site (eq. LimGenF): trimming (eq. entrHom / Ehrenfests'
 // step) and the median filter (Sec. 3.5); both on -> the smaller phi.
 template <class A>
-__device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const DomainDev& D, unsigned& mask)
+__device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const DomainDev& D, unsigned& mask, A& tgt)
 {
     A phi = A(1);
+    tgt = A(__builtin_huge_val());
     if (D.limiter & kLimTrim) {
         A t = A(D.delta_trim);
         if (dpost > t) {
             mask |= kMaskTrim;
             A p = D.trim_mode ? A(0) : sqrt_(t * rcp(dpost));
             phi = fmin(phi, p);
+            if (!D.trim_mode) tgt = fmin(tgt, t);
         }
     }
     if ((D.limiter & kLimMedian) && has_med) {
@@ -515,6 +517,7 @@ __device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const Dom
         if (hit) {
             mask |= kMaskMedian;
             phi = fmin(phi, sqrt_(t * rcp(dpost)));
+            tgt = fmin(tgt, t);
         }
     }
     return phi;
@@ -676,23 +679,39 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
     }
 }
 
-// Factor of the ensemble-dependent limiters for a node with Delta S' = d,
-// from this step's E(Delta S') and thresholds (ens[kNEns]); 1 when none moves
-// the node.  Threshold and budget: homothety to Delta S_t above it (eq.
-// entrHom); smooth: eq. (smooth1) with a = delta / E^k; rational: eq.
-// (phiExamp) with r = d / (alpha E), kept <= 1 (only entropic moves).
-// +inf (a non-positive population) gives 0; NaN gives 1.
+// Second-pass limiter terms of a node with Delta S' = d, from this step's
+// E(Delta S') and thresholds (ens[kNEns]): `tgt`, the smallest homothety
+// target Delta S_t among the limiters that act (threshold and budget: eq.
+// entrHom above Delta S_t; top-k trimming in homothety mode: delta), and
+// `fac`, the smallest factor given as phi itself (smooth: eq. (smooth1) with
+// a = delta / E^k; rational: eq. (phiExamp) with r = d / (alpha E), kept <= 1;
+// top-k Ehrenfests' step: 0).  The node's factor is min(fac, phi(tgt)), with
+// phi(tgt) = sqrt(tgt / d) in the quadratic reading of the homothety.
+// +inf (a non-positive population) gives 0; NaN moves nothing.
+struct SecondHit {
+    unsigned bits = 0;
+    int ens = 0, trim = 0;
+};
 template <class A>
-__device__ __forceinline__ A ens_phi(const DomainDev& D, const double* ens, A d)
+__device__ __forceinline__ void ens_terms(const DomainDev& D, const double* ens, A d, A& tgt, A& fac, SecondHit& h)
 {
-    A pe = A(1);
     const int lim = D.limiter;
-    if ((lim & kLimEnsThresh) && d > A(ens[kEThresh])) pe = fmin(pe, sqrt_(A(ens[kEThresh]) * rcp(d)));
-    if ((lim & kLimEnsBudget) && d > A(ens[kEBudget])) pe = fmin(pe, sqrt_(A(ens[kEBudget]) * rcp(d)));
+    bool e = false;
+    if ((lim & kLimEnsThresh) && d > A(ens[kEThresh])) {
+        tgt = fmin(tgt, A(ens[kEThresh]));
+        e = true;
+    }
+    if ((lim & kLimEnsBudget) && d > A(ens[kEBudget])) {
+        tgt = fmin(tgt, A(ens[kEBudget]));
+        e = true;
+    }
     const double mean = ens[kEMean];
     if ((lim & kLimEnsSmooth) && mean > 0.0 && d > A(0)) {
         const A v = isinf(d) ? A(0) : A(1) / (A(1) + A(ens[kESmoothA]) * pow_(d, A(D.ens_k)));
-        pe = fmin(pe, v);
+        if (v < A(1)) {
+            fac = fmin(fac, v);
+            e = true;
+        }
     }
     if ((lim & kLimEnsRational) && mean > 0.0 && d > A(0)) {
         A v = A(0);
@@ -700,9 +719,72 @@ __device__ __forceinline__ A ens_phi(const DomainDev& D, const double* ens, A d)
             const A r = d / A(D.ens_c * mean);
             v = (A(1) + pow_(r, A(D.ens_k - 0.5))) / (A(1) + pow_(r, A(D.ens_k)));
         }
-        pe = fmin(pe, v);
+        if (v < A(1)) {
+            fac = fmin(fac, v);
+            e = true;
+        }
     }
-    return pe;
+    if (e) {
+        h.bits |= kMaskEns;
+        ++h.ens;
+    }
+    if ((lim & kLimTopK) && d > A(D.delta_trim) && (isinf(d) || d >= A(ens[kETopk]))) {
+        h.bits |= kMaskTrim;
+        ++h.trim;
+        if (D.trim_mode) fac = A(0);
+        else tgt = fmin(tgt, A(D.delta_trim));
+    }
+}
+
+// Root p >= 0 of F(p) = sum f*_i h(p x_i) = t (the Kullback Delta S of the
+// state whose deviation from f* is p x), F convex and increasing: Newton
+// from p0 inside [lo, hi] (bisection when a step leaves the bracket), then
+// moved down to F(p) <= t.  Used for the homothety to Delta S_t with the
+// exact Delta S (Sec. 3.6: phi with S(f* + phi (f - f*)) = S(f*) - Delta S_t).
+template <int Q, class A>
+__device__ A kullback_scale(const A (&fs)[Q], const A (&x)[Q], A t, A p0, A lo, A hi)
+{
+    constexpr A eps = sizeof(A) == 8 ? A(2.220446049250313e-16) : A(1.1920929e-7);
+    auto F = [&](A p) {
+        A s = A(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += fs[i] * h_closed(p * x[i]);
+        return s;
+    };
+    A p = fmin(fmax(p0, lo), hi);
+    for (int it = 0; it < 60; ++it) {
+        A f = -t, df = A(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const A y = p * x[i];
+            f += fs[i] * h_closed(y);
+            df += fs[i] * x[i] * log1p(fmax(y, A(-1)));
+        }
+        if (f <= A(0)) lo = p;
+        else hi = p;
+        A pn = p - f / df;
+        if (!(pn > lo && pn < hi)) pn = A(0.5) * (lo + hi);
+        const bool done = fabs(pn - p) <= A(2) * eps * p;
+        p = pn;
+        if (done) break;
+    }
+    for (int k = 0; k < 4 && F(p) > t; ++k) p *= A(1) - A(2) * eps;
+    if (F(p) > t) p = lo;
+    return p;
+}
+
+// exact homothety of a post-collision state (f' - f* = -c d) to Delta S = t
+template <int LAT, class A>
+__device__ __forceinline__ A exact_homothety(const SiteState<LAT, A>& o, A shift, A t, A dpost)
+{
+    using L = Lat<LAT>;
+    A fs[L::Q], x[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        fs[i] = A(L::w(i)) * shift + o.gs[i];
+        x[i] = -o.c * o.d[i] / fs[i];
+    }
+    return kullback_scale<L::Q>(fs, x, t, sqrt_(t * rcp(dpost)), A(0), A(1));
 }
 
 constexpr int kSmallDomainTiles = 32;

@@ -249,6 +249,10 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                 }
                 unsigned mask = 0;
                 A phi = trim_phi(D, S.dpost, mask);
+                if constexpr (DS == kExact) {
+                    if (D.homothety && (mask & kMaskTrim) && !D.trim_mode && isfinite(S.dpost))
+                        phi = exact_homothety<kD2Q9>(S, shift, A(D.delta_trim), S.dpost);
+                }
                 if (S.posrule) {
                     mask |= kMaskPos;
                     ++acc.pos;
@@ -406,6 +410,7 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                 if (D.limiter & (kLimEnsSmooth | kLimEnsRational)) cand = cand || rp[kSFluid] > 0.0;
                 if (D.limiter & kLimEnsThresh) cand = cand || inf || mx > A(ensv[kEThresh]);
                 if (D.limiter & kLimEnsBudget) cand = cand || inf || mx > A(ensv[kEBudget]);
+                if (D.limiter & kLimTopK) cand = cand || inf || mx > A(D.delta_trim);
             }
         }
         active = __syncthreads_or(cand);
@@ -488,38 +493,35 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             for (int k = 0; k < kMedChunk; ++k) {
                 const int y = yb + k;
                 const A dc = w[k + 1][1];
-                A pm = A(1), thr;
-                bool med = false;
-                if ((D.limiter & kLimMedian) && y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid &&
-                    median_hit<BC>(D, x, y, nx, ny, w[k], w[k + 1], w[k + 2], thr)) {
-                    med = true;
-                    pm = sqrt_(thr * rcp(dc));
+                auto fluid = [&] { return y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid; };
+                // smallest homothety target and smallest direct factor of the
+                // limiters that act on this node (relative to f')
+                A tgt = A(__builtin_huge_val()), fac = A(1), thr;
+                SecondHit h;
+                if ((D.limiter & kLimMedian) && fluid() && median_hit<BC>(D, x, y, nx, ny, w[k], w[k + 1], w[k + 2], thr)) {
+                    h.bits |= kMaskMedian;
+                    tgt = thr;
                 }
-                A pe = A(1);
                 if constexpr (ENS) {
-                    if ((D.limiter & kLimEns) && y < t.y1 && node_class<BC>(x, y, nx, ny) == kNodeFluid)
-                        pe = ens_phi(D, ensv, dc);
+                    if ((D.limiter & kLimEns) && fluid()) ens_terms(D, ensv, dc, tgt, fac, h);
                 }
-                if (med || pe < A(1)) {
-                    unsigned bits = 0;
-                    if (med) {
-                        ++acc.filt;
-                        bits |= kMaskMedian;
-                    }
-                    if (pe < A(1)) {
-                        ++acc.ens;
-                        bits |= kMaskEns;
-                        pm = fmin(pm, pe);
-                    }
-                    unsigned tmask = 0;
-                    const A pt = trim_phi(D, dc, tmask);
+                if (h.bits) {
+                    if (h.bits & kMaskMedian) ++acc.filt;
+                    acc.ens += h.ens;
+                    acc.trim += h.trim;
                     const long long rc = (long long)y * nx;
-                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)bits;
-                    if (pm < pt) {
-                        // the filter lowers phi: rescale the limited state that
-                        // the collision kernel stored at this node toward its f*,
-                        // rebuilt from the state's own moments (the limiter kept
-                        // them): f* + (pm / pt)(f_stored - f*)
+                    if (record) to_global<unsigned char>(D.mask)[unsigned(rc) + unsigned(x)] |= (unsigned char)h.bits;
+                    unsigned tmask = 0;
+                    // the factor the collision kernel applied (trimming)
+                    const A pt = trim_phi(D, dc, tmask);
+                    const A pq = fmin(fac, tgt < A(__builtin_huge_val()) ? sqrt_(tgt * rcp(dc)) : A(1));
+                    bool exact = false;
+                    if constexpr (DS == kExact) exact = D.homothety && isfinite(dc);
+                    if (exact || pq < pt) {
+                        // the second pass lowers phi: rescale the limited state
+                        // that the collision kernel stored at this node toward its
+                        // f*, rebuilt from the state's own moments (the limiter
+                        // kept them): f* + r (f_stored - f*)
                         const gptr<const T> lsrc = to_global<T>(static_cast<const void*>(D.buf[1 - a.parity]));
                         const gptr<T> dst = to_global<T>(D.buf[1 - a.parity]);
                         const unsigned own = unsigned(sizeof(T)) * unsigned(x);
@@ -528,28 +530,60 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                         for (int i = 0; i < Q; ++i) gl[i] = Store<T>::ld(at_bytes(lsrc + (i * plane + rc), own));
                         A dr, jx, jy, rho, ux, uy;
                         moments_equilibrium<kD2Q9, QE>(gl, shift, dr, jx, jy, rho, ux, uy, gs);
-                        const A r = pm * rcp(pt);
+                        A r = pq * rcp(pt);
+                        // deviation of the stored state (exact Delta S only)
+                        A fs[DS == kExact ? Q : 1], e[DS == kExact ? Q : 1];
+                        if constexpr (DS == kExact) {
 #pragma unroll
-                        for (int i = 0; i < Q; ++i)
-                            Store<T>::st(at_bytes(dst + (i * plane + rc), own), gs[i] + r * (gl[i] - gs[i]));
-                        if (isfinite(dc)) {
-                            // limiter entropy production: replace the trimming share
-                            A ds_pm, ds_pt;
-                            if constexpr (DS == kQuad) {
-                                ds_pm = pm * pm * dc;
-                                ds_pt = pt * pt * dc;
-                            } else {
-                                ds_pm = ds_pt = A(0);
+                            for (int i = 0; i < Q; ++i) {
+                                fs[i] = A(Lat<kD2Q9>::w(i)) * shift + gs[i];
+                                e[i] = (gl[i] - gs[i]) * rcp(fs[i]);
+                            }
+                            if (exact) {
+                                // exact homothety (Sec. 3.6): the stored state's
+                                // deviation e = pt x; reach the target from it, and
+                                // take direct factors relative to f' = f* + e / pt
+                                A ds_s = A(0), emin = A(0);
 #pragma unroll
                                 for (int i = 0; i < Q; ++i) {
-                                    const A fs = A(Lat<kD2Q9>::w(i)) * shift + gs[i];
-                                    const A e = (gl[i] - gs[i]) * rcp(fs);
-                                    ds_pt += fs * hkern(e);
-                                    ds_pm += fs * hkern(r * e);
+                                    ds_s += fs[i] * hkern(e[i]);
+                                    emin = fmin(emin, e[i]);
+                                }
+                                r = A(1);
+                                if (ds_s > A(0)) {
+                                    if (tgt < ds_s)
+                                        r = kullback_scale<Q>(fs, e, tgt, sqrt_(tgt * rcp(ds_s)), A(0), A(1));
+                                    if (fac < A(1)) {
+                                        const A lmax = emin < A(0) ? A(-1) / emin : A(__builtin_huge_val());
+                                        const A lam = pt < A(1)
+                                                          ? kullback_scale<Q>(fs, e, dc, sqrt_(dc * rcp(ds_s)), A(1), lmax)
+                                                          : A(1);
+                                        r = fmin(r, fac * lam);
+                                    }
                                 }
                             }
-                            const A before = pt < A(1) ? dc - ds_pt : A(0);
-                            acc.lim += (dc - ds_pm) - before;
+                        }
+                        if (r < A(1)) {
+#pragma unroll
+                            for (int i = 0; i < Q; ++i)
+                                Store<T>::st(at_bytes(dst + (i * plane + rc), own), gs[i] + r * (gl[i] - gs[i]));
+                            if (isfinite(dc)) {
+                                // limiter entropy production: Delta S of the stored
+                                // state minus Delta S of the new one
+                                A ds_new, ds_old;
+                                if constexpr (DS == kQuad) {
+                                    ds_new = r * r * pt * pt * dc;
+                                    ds_old = pt * pt * dc;
+                                } else {
+                                    ds_new = ds_old = A(0);
+#pragma unroll
+                                    for (int i = 0; i < Q; ++i) {
+                                        ds_old += fs[i] * hkern(e[i]);
+                                        ds_new += fs[i] * hkern(r * e[i]);
+                                    }
+                                }
+                                acc.lim += ds_old - ds_new;
+                            }
                         }
                     }
                 }
@@ -656,7 +690,12 @@ __global__ void __launch_bounds__(kThreads) k_step1d(StepArgs a)
         unsigned mask = 0;
         const bool has_med = (D.limiter & kLimMedian) && (BC == kPeriodic || (x >= 1 && x <= nx - 2));
         const A med = has_med ? med3(ds[tid - 1], ds[tid], ds[tid + 1]) : A(0);
-        A phi = limiter_phi(S.dpost, has_med, med, D, mask);
+        A tgt;
+        A phi = limiter_phi(S.dpost, has_med, med, D, mask, tgt);
+        if constexpr (DS == kExact) {
+            if (D.homothety && phi > A(0) && tgt < A(__builtin_huge_val()) && isfinite(S.dpost))
+                phi = exact_homothety<LAT>(S, shift, tgt, S.dpost);
+        }
         if (S.posrule) {
             mask |= kMaskPos;
             ++acc.pos;
@@ -711,11 +750,17 @@ __global__ void __launch_bounds__(kThreads) k_ens1d(StepArgs a)
         for (int k = 0; k < kNEns; ++k) ensv[k] = D.ens[k];
         const A d = Store<A>::ld(to_global<A>(static_cast<const void*>(D.dsbuf)) + x);
         const A pa = Store<A>::ld(to_global<A>(static_cast<const void*>(D.phibuf)) + x);
-        const A pe = ens_phi(D, ensv, d);
-        if (pe < A(1)) {
-            ++acc.ens;
-            if (a.flags & kFlagRecord) to_global<unsigned char>(D.mask)[x] |= (unsigned char)kMaskEns;
-            if (pe < pa) {
+        A tgt = A(__builtin_huge_val()), fac = A(1);
+        SecondHit h;
+        ens_terms(D, ensv, d, tgt, fac, h);
+        if (h.bits) {
+            acc.ens += h.ens;
+            acc.trim += h.trim;
+            if (a.flags & kFlagRecord) to_global<unsigned char>(D.mask)[x] |= (unsigned char)h.bits;
+            const A pq = fmin(fac, tgt < A(__builtin_huge_val()) ? sqrt_(tgt * rcp(d)) : A(1));
+            bool exact = false;
+            if constexpr (DS == kExact) exact = D.homothety && isfinite(d) && pa > A(0);
+            if (exact || pq < pa) {
                 const long long plane = D.plane;
                 const A shift = A(D.shift);
                 const gptr<const T> lsrc = to_global<T>(static_cast<const void*>(D.buf[1 - a.parity]));
@@ -725,26 +770,43 @@ __global__ void __launch_bounds__(kThreads) k_ens1d(StepArgs a)
                 for (int i = 0; i < Q; ++i) gl[i] = Store<T>::ld(lsrc + (i * plane + x));
                 A dr, jx, jy, rho, ux, uy;
                 moments_equilibrium<LAT, QE>(gl, shift, dr, jx, jy, rho, ux, uy, gs);
-                const A r = pe * rcp(pa);
+                A fs[Q], e[Q];
 #pragma unroll
-                for (int i = 0; i < Q; ++i) Store<T>::st(dst + (i * plane + x), gs[i] + r * (gl[i] - gs[i]));
-                if (isfinite(d)) {
-                    A ds_pe, ds_pa;
-                    if constexpr (DS == kQuad) {
-                        ds_pe = pe * pe * d;
-                        ds_pa = pa * pa * d;
-                    } else {
-                        ds_pe = ds_pa = A(0);
+                for (int i = 0; i < Q; ++i) {
+                    fs[i] = A(Lat<LAT>::w(i)) * shift + gs[i];
+                    e[i] = (gl[i] - gs[i]) * rcp(fs[i]);
+                }
+                A r = pq * rcp(pa);
+                if constexpr (DS == kExact) {
+                    if (exact) {
+                        // exact homothety from f' = f* + e / pa (Sec. 3.6)
+                        A xp[Q];
 #pragma unroll
-                        for (int i = 0; i < Q; ++i) {
-                            const A fs = A(Lat<LAT>::w(i)) * shift + gs[i];
-                            const A e = (gl[i] - gs[i]) * rcp(fs);
-                            ds_pa += fs * hkern(e);
-                            ds_pe += fs * hkern(r * e);
-                        }
+                        for (int i = 0; i < Q; ++i) xp[i] = e[i] / pa;
+                        A ph = fac;
+                        if (tgt < d) ph = fmin(ph, kullback_scale<Q>(fs, xp, tgt, sqrt_(tgt * rcp(d)), A(0), A(1)));
+                        r = ph / pa;
                     }
-                    // the step kernel counted d - Delta S(phi_applied)
-                    acc.lim += ds_pa - ds_pe;
+                }
+                if (r < A(1)) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) Store<T>::st(dst + (i * plane + x), gs[i] + r * (gl[i] - gs[i]));
+                    if (isfinite(d)) {
+                        A ds_old, ds_new;
+                        if constexpr (DS == kQuad) {
+                            ds_old = pa * pa * d;
+                            ds_new = r * r * pa * pa * d;
+                        } else {
+                            ds_old = ds_new = A(0);
+#pragma unroll
+                            for (int i = 0; i < Q; ++i) {
+                                ds_old += fs[i] * hkern(e[i]);
+                                ds_new += fs[i] * hkern(r * e[i]);
+                            }
+                        }
+                        // the step kernel counted d - Delta S(stored)
+                        acc.lim += ds_old - ds_new;
+                    }
                 }
             }
         }

@@ -56,7 +56,7 @@ class lbm_domain_desc(ctypes.Structure):
         ("rho_init", _dp), ("u_init", _dp), ("f_init", _dp),
         ("probe_x", ctypes.c_int32), ("probe_y", ctypes.c_int32),
         ("ens_c", ctypes.c_double), ("ens_k", ctypes.c_double), ("delta_ens", ctypes.c_double),
-        ("collision", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("homothety", ctypes.c_int32), ("top_k", ctypes.c_int64),
     ]
 
 
@@ -171,6 +171,8 @@ class Domain:
     ens_k: float = 0.5
     delta_ens: float = 0.0
     collision: int = LBM_COLL_LBGK
+    homothety: int = 0
+    top_k: int = 0
     rho_init: np.ndarray | None = None
     u_init: np.ndarray | None = None
     f_init: np.ndarray | None = None
@@ -192,7 +194,8 @@ class Domain:
         d = lbm_domain_desc()
         d.struct_size = ctypes.sizeof(lbm_domain_desc)
         for k in ("lattice", "nx", "ny", "beta", "qe", "limiter", "trim_mode", "median_mode", "ds_form", "bc",
-                  "delta_trim", "delta_median", "rho0", "lid_ux", "ens_c", "ens_k", "delta_ens", "collision"):
+                  "delta_trim", "delta_median", "rho0", "lid_ux", "ens_c", "ens_k", "delta_ens", "collision",
+                  "homothety", "top_k"):
             setattr(d, k, getattr(self, k))
         self._keep = []
         for name, arr, size in (("rho_init", self.rho_init, n), ("u_init", self.u_init, self.dim * n),

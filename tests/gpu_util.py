@@ -32,7 +32,7 @@ def oracle_params(d, entropy=False):
                          limiter=d.limiter, trim_mode=d.trim_mode, median_mode=d.median_mode, bc=d.bc,
                          delta_trim=d.delta_trim, delta_median=d.delta_median, rho0=d.rho0, lid_ux=d.lid_ux,
                          entropy=entropy, ens_c=d.ens_c, ens_k=d.ens_k, delta_ens=d.delta_ens,
-                         collision=d.collision)
+                         collision=d.collision, homothety=d.homothety, top_k=d.top_k)
 
 
 def say(*a):
