@@ -54,6 +54,23 @@ def critical_reynolds(re, e2, frac: float = 0.05):
     return float(-icpt / slope), float(slope), [float(r) for r in re[osc]]
 
 
+def onset(re, e2, frac: float = 0.05):
+    """(largest Re of a steady run below the smallest Re of an oscillating
+    one, that smallest Re): the bracket of the transition when the
+    oscillation appears with a finite amplitude (E_u^2 above `frac` of the
+    largest counts as oscillating)"""
+    re = np.asarray(re, dtype=np.float64)
+    e2 = np.asarray(e2, dtype=np.float64)
+    if not e2.size or e2.max() <= 0:
+        return math.nan, math.nan
+    osc = e2 > frac * e2.max()
+    if not osc.any():
+        return math.nan, math.nan
+    first = float(re[osc].min())
+    below = re[(~osc) & (re < first)]
+    return (float(below.max()) if below.size else math.nan), first
+
+
 def dominant_frequency(u_sig, length: float, u0: float) -> float:
     """cycles per non-dimensional time unit of the largest spectral peak
     (Hann window, mean removed, rest frequency excluded)"""
@@ -109,6 +126,7 @@ def run(L, re_values, n: int = 100, u0: float = 0.1, time_units: float = 5000.0,
     out["earlier_window_end"] = 1.0 - (cap - keep) / steps
     e2 = [v * v for v in e]
     rec, slope, used = critical_reynolds(re_values, e2)
+    out["onset"] = list(onset(re_values, e2))
     out.update({
         "E_u": e, "E_u2": e2, "Re_c": rec, "slope": slope, "fit_re": used,
         "frequency": [dominant_frequency(s[:, 0], n, u0) for s in sig],

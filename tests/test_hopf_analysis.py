@@ -45,3 +45,11 @@ def test_dominant_frequency():
 def test_probe_node():
     assert hopf.probe_node(100) == (6, 80)
     assert hopf.probe_node(17) == (1, 13)
+
+
+def test_onset_bracket():
+    re = [6000.0, 6250.0, 6300.0, 6350.0, 6500.0]
+    e2 = [7e-8, 7.6e-8, 8e-8, 9e-4, 1e-3]
+    assert hopf.onset(re, e2) == (6300.0, 6350.0)
+    lo, hi = hopf.onset(re, [0.0] * 5)
+    assert math.isnan(lo) and math.isnan(hi)
