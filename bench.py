@@ -49,7 +49,7 @@ BYTES_PER_SITE = {0: 144, 1: 72, 2: 36, 3: 36}     # read Q + write Q population
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide2d_f32_4096.json")
 KERNEL_SOURCES = ["paper_0704_0043_amd/csrc/step.hip", "paper_0704_0043_amd/csrc/lbm_device.h",
                   "paper_0704_0043_amd/csrc/lbm_common.h"]
-DOMINANT = "k_collide2d<float, 0, 1, 0>"
+DOMINANT = "k_collide2d<float, 0, 1, 0, false>"
 COPY_BYTES = 1 << 30
 
 

@@ -381,6 +381,29 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
     AccT<A> acc;
     const int nx = D.nx, ny = D.ny;
     const int x = t.x0 + int(threadIdx.x);
+    // rows y0-1 .. y1 are read; y1 <= ny, so one wrap keeps them in range
+    auto row_of = [&](int y) -> int {
+        if constexpr (BC == kPeriodic)
+            return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        else
+            return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+    };
+    // FLOOR median only: the 64 columns of a collision wave in which no node
+    // exceeded delta hold no Delta S' of this step and read as zeros.  Which
+    // waves stored (bit w of the segment's candidate count) is staged in LDS
+    // for the tile's rows and halo rows, for its own column strip and the two
+    // neighbouring ones: [0] left, [1] own, [2] right.
+    const bool sparse = !((D.limiter & kLimEns) || D.median_mode != 0);
+    __shared__ int sflag[3][kMaxTileH + 2];
+    const int strip = t.x0 / kThreads;
+    int strip_l, strip_r;
+    if constexpr (BC == kPeriodic) {
+        strip_l = (t.x0 == 0 ? nx - 1 : t.x0 - 1) / kThreads;
+        strip_r = (t.x1 == nx ? 0 : t.x1) / kThreads;
+    } else {
+        strip_l = (t.x0 == 0 ? 0 : t.x0 - 1) / kThreads;
+        strip_r = (t.x1 == nx ? nx - 1 : t.x1) / kThreads;
+    }
     // The filter's threshold is never below delta (FLOOR: max(median, delta);
     // GATE: only nodes above delta), so a tile none of whose nodes has
     // Delta S' > delta (the collision kernel counted them, in the same
@@ -413,6 +436,15 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                 if (D.limiter & kLimTopK) cand = cand || inf || mx > A(D.delta_trim);
             }
         }
+        if ((D.limiter & kLimMedian) && sparse) {
+            const int nr = rows + 2;
+            for (int idx = int(threadIdx.x); idx < 3 * nr; idx += kThreads) {
+                const int slot = idx / nr, ry = idx - slot * nr;
+                const int s3 = slot == 0 ? strip_l : (slot == 1 ? strip : strip_r);
+                const long long seg = (long long)D.row_first + (long long)row_of(t.y0 - 1 + ry) * D.strips + s3;
+                sflag[slot][ry] = int(a.rowpart[seg * kNStat + kSAbove]);
+            }
+        }
         active = __syncthreads_or(cand);
     }
     if (active && x < t.x1) {
@@ -429,22 +461,9 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             xm = x > 0 ? x - 1 : x;
             xp = x < nx - 1 ? x + 1 : x;
         }
-        // rows y0-1 .. y1 are read; y1 <= ny, so one wrap keeps them in range
-        auto row_of = [&](int y) -> int {
-            if constexpr (BC == kPeriodic)
-                return y < 0 ? y + ny : (y >= ny ? y - ny : y);
-            else
-                return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
-        };
-        // FLOOR median only: the 64 columns of a collision wave in which no
-        // node exceeded delta hold no Delta S' of this step and read as zeros
-        // (bit w of a segment's count of such nodes: wave w stored)
-        const bool sparse = !((D.limiter & kLimEns) || D.median_mode != 0);
         const int sx = x / kThreads, sxm = xm / kThreads, sxp = xp / kThreads;
         const int wx = (x % kThreads) / kWave, wxm = (xm % kThreads) / kWave, wxp = (xp % kThreads) / kWave;
-        auto stored = [&](const double* rp, int strip, int w) {
-            return (int(rp[strip * kNStat]) >> w) & 1;
-        };
+        const int slot_m = sxm == sx ? 1 : 0, slot_p = sxp == sx ? 1 : 2;
         // Each lane loads its own column (one aligned load per row); the
         // columns x -+ 1 come from the neighbouring lanes.  Only the first
         // lane of a wave and the lane at the right end of a wave or of the
@@ -459,10 +478,10 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             if (own_l) r[0] = Store<A>::ld(dsb + (rr + xm));
             if (own_r) r[2] = Store<A>::ld(dsb + (rr + xp));
             if (sparse) {
-                const double* rp = a.rowpart + ((long long)D.row_first + (long long)yy * D.strips) * kNStat + kSAbove;
-                if (!stored(rp, sx, wx)) r[1] = A(0);
-                if (own_l && !stored(rp, sxm, wxm)) r[0] = A(0);
-                if (own_r && !stored(rp, sxp, wxp)) r[2] = A(0);
+                const int ry = y - (t.y0 - 1);
+                if (!((sflag[1][ry] >> wx) & 1)) r[1] = A(0);
+                if (own_l && !((sflag[slot_m][ry] >> wxm) & 1)) r[0] = A(0);
+                if (own_r && !((sflag[slot_p][ry] >> wxp) & 1)) r[2] = A(0);
             }
         };
         auto complete = [&](A (&r)[3]) {
