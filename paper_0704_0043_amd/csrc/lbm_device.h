@@ -319,8 +319,8 @@ __device__ __forceinline__ A h_closed(A y)
 // G(s) = sum f*_i h(-s x_i) - sum f*_i h(x_i) = 0 with G convex and
 // increasing on [0, s_max], s_max the positivity boundary of f~.  Newton from
 // the LBGK mirror s = 1, kept inside the bracket (bisection when a step
-// leaves it); the result is moved down to a point with G <= 0, so the
-// entropy does not decrease.  No root short of s_max (or a state f without
+// leaves it), until G is at the rounding level of its sums; the result is
+// moved down to a point with G <= 0, so the entropy does not decrease.  No root short of s_max (or a state f without
 // entropy): the positivity rule, s = s_max.
 template <int Q, class A>
 __device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
@@ -356,6 +356,8 @@ __device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
             g += fs[i] * h_closed(y);
             dg -= fs[i] * x[i] * log1p(fmax(y, A(-1)));
         }
+        // at the rounding level of the sums: the root is as good as it gets
+        if (fabs(g) <= A(4) * eps * target) break;
         if (g <= A(0)) lo = s;
         else hi = s;
         A sn = s - g / dg;
@@ -760,6 +762,7 @@ __device__ A kullback_scale(const A (&fs)[Q], const A (&x)[Q], A t, A p0, A lo, 
             f += fs[i] * h_closed(y);
             df += fs[i] * x[i] * log1p(fmax(y, A(-1)));
         }
+        if (fabs(f) <= A(4) * eps * t) break;
         if (f <= A(0)) lo = p;
         else hi = p;
         A pn = p - f / df;
