@@ -6,7 +6,7 @@ entropy trimming and the 3x3 median filter both on (delta = 1e-4),
 polynomial f*, quadratic Delta S.  One step = the collision kernel (free
 flight, moments, f*, over-relaxation, Delta S', trimming, store, one partial
 of the reduction terms per workgroup) plus the median kernel (3x3 median of
-Delta S', the filtered nodes collided again); steps run as captured HIP
+Delta S', the filtered nodes rescaled in place); steps run as captured HIP
 graphs, and the FP64 global stats of the last step are formed inside the
 timed region.
 

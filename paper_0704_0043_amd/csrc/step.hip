@@ -1,22 +1,23 @@
 // Fused limited LBGK step kernels for gfx950.
 //
 // Compiled once per population storage type (LBM_ST = 0..3).  A D2Q9 time
-// step of every domain is one launch of the collision kernel and, when the
-// median filter is on, one launch of the median kernel:
+// step of every domain is one launch of the collision kernel and, when a
+// limiter needs more than the node itself, one launch of the second pass:
 //
 //  collision: one thread per node, one workgroup per row segment of 256
 //    columns, segments in row-major order, so the whole grid streams through
 //    a narrow band of rows at a time.  Free flight (pull form, read from
-//    buffer `parity`), moments, f*, over-relaxation, Delta S', the trimming
-//    factor (it depends on the node alone), and the store of the limited
-//    post-collision state into the other buffer.  With the median filter on,
-//    Delta S' also goes to a plane of its own.  Each workgroup leaves one
-//    partial of the reduction terms; the FP64 global sums are formed from
-//    these on demand, when the stats are read.
-//  median: the 3x3 median of that plane decides the filter; the few nodes
-//    whose factor drops below the trimming factor are collided again (the
-//    same arithmetic, bit-identical) from the untouched source buffer and
-//    overwritten.
+//    buffer `parity`), moments, f*, the collision (LBGK, or ELBM in its own
+//    instantiation), Delta S', the trimming and positivity factors (they
+//    depend on the node alone), and the store of the limited post-collision
+//    state into the other buffer.  With the median filter or an
+//    ensemble-dependent limiter on, Delta S' also goes to a plane of its own.
+//    Each workgroup leaves one partial of the reduction terms; the FP64
+//    global sums are formed from these on demand, when the stats are read.
+//  second pass: the 3x3 median of that plane and the ensemble-dependent
+//    factors (thresholds from this step's E(Delta S') and selections) decide
+//    which nodes move further; their stored limited states are rescaled
+//    toward f* in place.
 //
 // The collision kernel is a plain streaming pass with aligned loads and
 // stores and no barrier before its epilogue, the access pattern that
@@ -322,12 +323,13 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     node_partial(acc, a.rowpart + (long long)ridx * kNStat, red);
 }
 
-// Median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the Delta S' plane
-// written by the collision kernel.  Each thread walks down its column in
-// chunks of kMedChunk rows: the loads of a whole chunk (three per row, L1- and
-// L2-resident for the neighbouring columns) are issued together, then the
-// medians of the chunk are taken from registers.  The rare nodes the filter
-// hits are handled after the chunk, one at a time.
+// Second pass: median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the
+// Delta S' plane written by the collision kernel, and the ensemble-dependent
+// limiters.  Each thread walks down its column in chunks of kMedChunk rows:
+// the loads of a whole chunk (one per row; the neighbouring columns come from
+// the adjacent lanes) are issued together, then the medians of the chunk are
+// taken from registers, row by row; a node that moves is rescaled on the spot
+// by its lane.
 constexpr int kMedChunk = 16;
 
 // the filter's threshold and decision for a node with Delta S' = dc whose
