@@ -54,10 +54,16 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources' code: comments and layout left out, so a
+    change of wording does not count as a change of the kernel."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
