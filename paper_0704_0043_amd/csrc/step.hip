@@ -331,6 +331,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
 // taken from registers, row by row; a node that moves is rescaled on the spot
 // by its lane.
 constexpr int kMedChunk = 16;
+constexpr int kPipe = 4;     // moved rows whose stored states are loaded together
 
 // the filter's threshold and decision for a node with Delta S' = dc whose
 // stencil median is med (FLOOR or GATE reading of the tolerance delta)
@@ -594,6 +595,8 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             // rows of the chunk in order; a node the median filter or an
             // ensemble limiter moves is handled on the spot by its lane (the
             // row's other lanes idle)
+            unsigned mv = 0;          // rows of the chunk this lane rescales afterwards
+            A rr[kMedChunk];          // their factor over the applied one
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k) {
                 const int y = yb + k;
@@ -622,15 +625,59 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                     const A pq = fmin(fac, tgt < A(__builtin_huge_val()) ? sqrt_(tgt * rcp(dc)) : A(1));
                     bool exact = false;
                     if constexpr (DS == kExact) exact = D.homothety && isfinite(dc);
-                    if (exact || pq < pt) {
-                        const gptr<T> buf = to_global<T>(D.buf[1 - a.parity]);
-                        const unsigned own = unsigned(sizeof(T)) * unsigned(x);
-                        if constexpr (DS == kExact)
+                    if constexpr (DS == kExact) {
+                        if (exact || pq < pt) {
+                            const gptr<T> buf = to_global<T>(D.buf[1 - a.parity]);
+                            const unsigned own = unsigned(sizeof(T)) * unsigned(x);
                             acc.lim += rescale_stored_exact<T, QE>(buf, plane, rc, own, shift, pq, pt, tgt, fac, dc,
                                                                    exact);
-                        else
+                        }
+                    } else if (pq < pt) {
+                        if constexpr (ENS) {
+                            // quadratic form with ensemble factors (often every
+                            // node moves): the factor is all the move needs, and
+                            // the rescale is done after the chunk's decisions
+                            mv |= 1u << k;
+                            rr[k] = pq * rcp(pt);
+                            if (isfinite(dc)) acc.lim += pt * pt * dc * (A(1) - rr[k] * rr[k]);
+                        } else {
+                            const gptr<T> buf = to_global<T>(D.buf[1 - a.parity]);
+                            const unsigned own = unsigned(sizeof(T)) * unsigned(x);
                             acc.lim += rescale_stored<T, QE, DS>(buf, plane, rc, own, shift, pq, pt, tgt, fac, dc,
                                                                  exact);
+                        }
+                    }
+                }
+            }
+            if constexpr (ENS && DS != kExact) {
+                // rescale the chunk's moved nodes kPipe rows at a time: the
+                // loads of those rows are in flight together
+                if (mv) {
+                    const gptr<T> buf = to_global<T>(D.buf[1 - a.parity]);
+                    const gptr<const T> lsrc = buf;
+                    const unsigned own = unsigned(sizeof(T)) * unsigned(x);
+#pragma unroll
+                    for (int k0 = 0; k0 < kMedChunk; k0 += kPipe) {
+                        A gl[kPipe][Q];
+#pragma unroll
+                        for (int u = 0; u < kPipe; ++u)
+                            if ((mv >> (k0 + u)) & 1u) {
+                                const long long rc = (long long)(yb + k0 + u) * nx;
+#pragma unroll
+                                for (int i = 0; i < Q; ++i)
+                                    gl[u][i] = Store<T>::ld(at_bytes(lsrc + (i * plane + rc), own));
+                            }
+#pragma unroll
+                        for (int u = 0; u < kPipe; ++u)
+                            if ((mv >> (k0 + u)) & 1u) {
+                                const long long rc = (long long)(yb + k0 + u) * nx;
+                                A gs[Q], dr, jx, jy, rho, ux, uy;
+                                moments_equilibrium<kD2Q9, QE>(gl[u], shift, dr, jx, jy, rho, ux, uy, gs);
+                                const A r = rr[k0 + u];
+#pragma unroll
+                                for (int i = 0; i < Q; ++i)
+                                    Store<T>::st(at_bytes(buf + (i * plane + rc), own), gs[i] + r * (gl[u][i] - gs[i]));
+                            }
                     }
                 }
             }
