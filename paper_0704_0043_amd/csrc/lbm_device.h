@@ -113,12 +113,16 @@ struct Store<double> {
     using A = double;
     __device__ static A ld(gptr<const double> p) { return *p; }
     __device__ static void st(gptr<double> p, A v) { *p = v; }
+    __device__ static void st_stream(gptr<double> p, A v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<float> {
     using A = float;
     __device__ static A ld(gptr<const float> p) { return *p; }
     __device__ static void st(gptr<float> p, A v) { *p = v; }
+    // streaming store (nontemporal hint): the state written by a step is not
+    // read again within it
+    __device__ static void st_stream(gptr<float> p, A v) { __builtin_nontemporal_store(v, p); }
 };
 // FP16 / BF16 storage uses the compiler's native _Float16 and __bf16 types
 // (round to nearest even on store).
@@ -127,12 +131,14 @@ struct Store<_Float16> {
     using A = float;
     __device__ static A ld(gptr<const _Float16> p) { return float(*p); }
     __device__ static void st(gptr<_Float16> p, A v) { *p = (_Float16)v; }
+    __device__ static void st_stream(gptr<_Float16> p, A v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <>
 struct Store<__bf16> {
     using A = float;
     __device__ static A ld(gptr<const __bf16> p) { return float(*p); }
     __device__ static void st(gptr<__bf16> p, A v) { *p = (__bf16)v; }
+    __device__ static void st_stream(gptr<__bf16> p, A v) { st(p, v); }
 };
 
 // ---- arithmetic helpers ------------------------------------------------------

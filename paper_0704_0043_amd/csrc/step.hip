@@ -159,7 +159,7 @@ __device__ __forceinline__ void store_limited(gptr<T> dst, long long plane, long
     using A = typename Store<T>::A;
     const A k = phi * c;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Store<T>::st(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
+    for (int i = 0; i < 9; ++i) Store<T>::st_stream(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
 }
 
 // Diffusive Maxwell wall node (Sec. 4.4.2), inward normal (mx, my), wall
