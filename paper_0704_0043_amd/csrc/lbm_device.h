@@ -199,6 +199,28 @@ __device__ inline float hkern(float x)
     return (1.0f + x) * log1pf(x) - x;
 }
 
+// h(x) with its derivative h'(x) = ln(1 + x).  Where hkern sums the series,
+// the logarithm follows from h itself, (1 + x) ln(1 + x) = h(x) + x, with no
+// cancellation (h is second order in x); elsewhere it is the logarithm that
+// h is built from.  h(-1) = 1 with h'(-1) = -inf (a population at zero).
+template <class A>
+__device__ inline A hkern_slope(A x, A& dh)
+{
+    constexpr A series = sizeof(A) == 8 ? A(0.1) : A(0.5);
+    if (x <= A(-1)) {
+        dh = -A(__builtin_huge_val());
+        return A(1);
+    }
+    if (fabs(x) <= series) {
+        const A h = hkern(x);
+        dh = (h + x) * rcp(A(1) + x);
+        return h;
+    }
+    const A l = log1p_(x);
+    dh = l;
+    return (A(1) + x) * l - x;
+}
+
 // ---- quasiequilibria, excess form -------------------------------------------
 // One axis of the entropic equilibrium: f*(v) / (rho w_v) = A B^v with
 // A = 2 - s, B = (2u + s)/(1 - u), s = sqrt(1 + 3u^2) (eq. maxwellian; the
@@ -323,11 +345,15 @@ __device__ __forceinline__ A h_closed(A y)
 // S(f*) - S(g) = sum f*_i h(x_i(g)) on the line through f and f*, and f~ has
 // the deviation (1 - alpha) x, so in s = alpha - 1 the equation is
 // G(s) = sum f*_i h(-s x_i) - sum f*_i h(x_i) = 0 with G convex and
-// increasing on [0, s_max], s_max the positivity boundary of f~.  Newton from
-// the LBGK mirror s = 1, kept inside the bracket (bisection when a step
-// leaves it), until G is at the rounding level of its sums; the result is
-// moved down to a point with G <= 0, so the entropy does not decrease.  No root short of s_max (or a state f without
-// entropy): the positivity rule, s = s_max.
+// increasing on [0, s_max], s_max the positivity boundary of f~, and
+// G(0) < 0.  Newton from the LBGK mirror s = 1, kept inside the bracket
+// (bisection when a step leaves it), until G is at the rounding level of its
+// sums; the result is moved down to a point with G <= 0, so the entropy does
+// not decrease.  A root short of s_max exists iff G(s_max) >= 0; that is
+// evaluated only when no iterate has found G > 0 by the time a step leaves
+// the bracket (on a convex G, a Newton step from a point with G < 0 lands at
+// or beyond the root).  No root (or a state f without entropy): the
+// positivity rule, s = s_max.
 template <int Q, class A>
 __device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
 {
@@ -343,37 +369,72 @@ __device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
     }
     posrule = false;
     if (!(smax < inf)) return A(2);        // f = f*: every alpha gives f
-    auto G = [&](A s) {
-        A g = -target;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) g += fs[i] * h_closed(-s * x[i]);
-        return g;
-    };
-    if (nonpos || G(smax) < A(0)) {
+    if (nonpos) {
         posrule = true;
         return A(1) + smax;
     }
-    A lo = A(0), hi = smax, s = fmin(A(1), A(0.5) * smax);
-    for (int it = 0; it < 60; ++it) {
-        A g = -target, dg = A(0);
+    // G(s) and G'(s) = -sum f*_i x_i ln(1 - s x_i)
+    auto eval = [&](A s, A& dg) {
+        A g = -target;
+        dg = A(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const A y = -s * x[i];
-            g += fs[i] * h_closed(y);
-            dg -= fs[i] * x[i] * log1p(fmax(y, A(-1)));
+            A dh;
+            g += fs[i] * hkern_slope(-s * x[i], dh);
+            dg -= fs[i] * x[i] * dh;
         }
+        return g;
+    };
+    A lo = A(0), hi = smax, s = fmin(A(1), A(0.5) * smax);
+    A g = A(0), dg;
+    bool at_s = false;      // g = G(s)
+    bool above = false;     // some G > 0 seen, or G(s_max) >= 0: a root lies in [lo, hi]
+    bool settled = false;   // converged (residual or step at the rounding level)
+    for (int it = 0; it < 60; ++it) {
+        g = eval(s, dg);
+        at_s = true;
         // at the rounding level of the sums: the root is as good as it gets
-        if (fabs(g) <= A(4) * eps * target) break;
-        if (g <= A(0)) lo = s;
-        else hi = s;
+        if (fabs(g) <= A(4) * eps * target) {
+            settled = true;
+            break;
+        }
+        if (g <= A(0)) {
+            lo = s;
+        } else {
+            hi = s;
+            above = true;
+        }
         A sn = s - g / dg;
-        if (!(sn > lo && sn < hi)) sn = A(0.5) * (lo + hi);
+        if (!(sn > lo && sn < hi)) {
+            if (!above) {
+                A d;
+                if (eval(smax, d) < A(0)) {
+                    posrule = true;
+                    return A(1) + smax;
+                }
+                above = true;
+            }
+            sn = A(0.5) * (lo + hi);
+        }
         const bool done = fabs(sn - s) <= A(2) * eps * s;
         s = sn;
-        if (done) break;
+        at_s = false;
+        if (done) {
+            settled = true;
+            break;
+        }
     }
-    for (int k = 0; k < 4 && G(s) > A(0); ++k) s *= A(1) - A(2) * eps;
-    if (G(s) > A(0)) s = lo;
+    A d;
+    if (!settled && !above && eval(smax, d) < A(0)) {
+        posrule = true;
+        return A(1) + smax;
+    }
+    A gs = at_s ? g : eval(s, d);
+    for (int k = 0; k < 4 && gs > A(0); ++k) {
+        s *= A(1) - A(2) * eps;
+        gs = eval(s, d);
+    }
+    if (gs > A(0)) s = lo;
     return A(1) + s;
 }
 
@@ -753,21 +814,24 @@ template <int Q, class A>
 __device__ A kullback_scale(const A (&fs)[Q], const A (&x)[Q], A t, A p0, A lo, A hi)
 {
     constexpr A eps = sizeof(A) == 8 ? A(2.220446049250313e-16) : A(1.1920929e-7);
-    auto F = [&](A p) {
-        A s = A(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) s += fs[i] * h_closed(p * x[i]);
-        return s;
-    };
-    A p = fmin(fmax(p0, lo), hi);
-    for (int it = 0; it < 60; ++it) {
-        A f = -t, df = A(0);
+    // F(p) - t and F'(p) = sum f*_i x_i ln(1 + p x_i)
+    auto eval = [&](A p, A& df) {
+        A f = -t;
+        df = A(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const A y = p * x[i];
-            f += fs[i] * h_closed(y);
-            df += fs[i] * x[i] * log1p(fmax(y, A(-1)));
+            A dh;
+            f += fs[i] * hkern_slope(p * x[i], dh);
+            df += fs[i] * x[i] * dh;
         }
+        return f;
+    };
+    A p = fmin(fmax(p0, lo), hi);
+    A f = A(0), df;
+    bool at_p = false;      // f = F(p) - t
+    for (int it = 0; it < 60; ++it) {
+        f = eval(p, df);
+        at_p = true;
         if (fabs(f) <= A(4) * eps * t) break;
         if (f <= A(0)) lo = p;
         else hi = p;
@@ -775,10 +839,16 @@ __device__ A kullback_scale(const A (&fs)[Q], const A (&x)[Q], A t, A p0, A lo, 
         if (!(pn > lo && pn < hi)) pn = A(0.5) * (lo + hi);
         const bool done = fabs(pn - p) <= A(2) * eps * p;
         p = pn;
+        at_p = false;
         if (done) break;
     }
-    for (int k = 0; k < 4 && F(p) > t; ++k) p *= A(1) - A(2) * eps;
-    if (F(p) > t) p = lo;
+    A d;
+    A fp = at_p ? f : eval(p, d);
+    for (int k = 0; k < 4 && fp > A(0); ++k) {
+        p *= A(1) - A(2) * eps;
+        fp = eval(p, d);
+    }
+    if (fp > A(0)) p = lo;
     return p;
 }
 
