@@ -327,10 +327,14 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
 // Delta S' plane written by the collision kernel, and the ensemble-dependent
 // limiters.  Each thread walks down its column in chunks of kMedChunk rows:
 // the loads of a whole chunk (one per row; the neighbouring columns come from
-// the adjacent lanes) are issued together, then the medians of the chunk are
-// taken from registers, row by row; a node that moves is rescaled on the spot
-// by its lane.
-constexpr int kMedChunk = 16;
+// the adjacent lanes) are issued together, then the decisions of the chunk
+// are taken from registers, row by row, and last the chunk's moved nodes are
+// rescaled with the loads of their stored states in flight together.  A node
+// rescaled on the spot would make every row of a wave wait for its loads and
+// for the acknowledgement of the previous row's stores; short chunks keep the
+// window and the deferred states in few enough registers for four waves per
+// SIMD.
+constexpr int kMedChunk = 4;
 constexpr int kPipe = 4;     // moved rows whose stored states are loaded together
 
 // the filter's threshold and decision for a node with Delta S' = dc whose
@@ -592,9 +596,10 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k)
                 if (yb + k + 1 <= t.y1) complete(w[k + 2]);
-            // rows of the chunk in order; a node the median filter or an
-            // ensemble limiter moves is handled on the spot by its lane (the
-            // row's other lanes idle)
+            // decisions for the rows of the chunk in order; with the exact
+            // Delta S a moved node is rescaled on the spot by its lane (its
+            // root solves are a real call), with the quadratic one after the
+            // chunk
             unsigned mv = 0;          // rows of the chunk this lane rescales afterwards
             A rr[kMedChunk];          // their factor over the applied one
 #pragma unroll
@@ -633,23 +638,16 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                                                                    exact);
                         }
                     } else if (pq < pt) {
-                        if constexpr (ENS) {
-                            // quadratic form with ensemble factors (often every
-                            // node moves): the factor is all the move needs, and
-                            // the rescale is done after the chunk's decisions
-                            mv |= 1u << k;
-                            rr[k] = pq * rcp(pt);
-                            if (isfinite(dc)) acc.lim += pt * pt * dc * (A(1) - rr[k] * rr[k]);
-                        } else {
-                            const gptr<T> buf = to_global<T>(D.buf[1 - a.parity]);
-                            const unsigned own = unsigned(sizeof(T)) * unsigned(x);
-                            acc.lim += rescale_stored<T, QE, DS>(buf, plane, rc, own, shift, pq, pt, tgt, fac, dc,
-                                                                 exact);
-                        }
+                        // quadratic form: the factor is all the move needs
+                        // (the limiter's entropy production follows from it),
+                        // and the rescale is done after the chunk's decisions
+                        mv |= 1u << k;
+                        rr[k] = pq * rcp(pt);
+                        if (isfinite(dc)) acc.lim += pt * pt * dc * (A(1) - rr[k] * rr[k]);
                     }
                 }
             }
-            if constexpr (ENS && DS != kExact) {
+            if constexpr (DS != kExact) {
                 // rescale the chunk's moved nodes kPipe rows at a time: the
                 // loads of those rows are in flight together
                 if (mv) {
