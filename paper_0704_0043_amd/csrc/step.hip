@@ -562,40 +562,50 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
         const int lane = int(threadIdx.x) & (kWave - 1);
         const bool own_l = lane == 0;
         const bool own_r = lane == kWave - 1 || x == t.x1 - 1;
-        auto load_own = [&](int y, A (&r)[3]) {
+        auto load_raw = [&](int y, A (&r)[3]) {
             const int yy = row_of(y);
             const long long rr = (long long)yy * nx;
             r[1] = Store<A>::ld(dsb + (rr + x));
             if (own_l) r[0] = Store<A>::ld(dsb + (rr + xm));
             if (own_r) r[2] = Store<A>::ld(dsb + (rr + xp));
+        };
+        // zeros for the columns of waves that stored nothing (FLOOR median),
+        // then the columns x -+ 1 from the neighbouring lanes
+        auto complete = [&](int y, A (&r)[3]) {
             if (sparse) {
                 const int ry = y - (t.y0 - 1);
                 if (!((sflag[1][ry] >> wx) & 1)) r[1] = A(0);
                 if (own_l && !((sflag[slot_m][ry] >> wxm) & 1)) r[0] = A(0);
                 if (own_r && !((sflag[slot_p][ry] >> wxp) & 1)) r[2] = A(0);
             }
-        };
-        auto complete = [&](A (&r)[3]) {
             // every active lane takes part in the shifts (no branch around them)
             const A l = lane_shift<-1>(r[1]), rr = lane_shift<+1>(r[1]);
             r[0] = own_l ? r[0] : l;
             r[2] = own_r ? r[2] : rr;
         };
-        // w[k] holds row yb - 1 + k of the current chunk
-        A w[kMedChunk + 2][3];
+        // w[k] holds row yb - 1 + k of the current chunk; the rows of the next
+        // chunk are loaded into nw before the current chunk's rescale, so
+        // waiting for them does not wait for that rescale's stores
+        A w[kMedChunk + 2][3], nw[kMedChunk][3];
 #pragma unroll
         for (int k = 0; k < kMedChunk + 2; ++k) w[k][0] = w[k][2] = A(0);
-        load_own(t.y0 - 1, w[0]);
-        load_own(t.y0, w[1]);
-        complete(w[0]);
-        complete(w[1]);
+#pragma unroll
+        for (int k = 0; k < kMedChunk; ++k) nw[k][0] = nw[k][1] = nw[k][2] = A(0);
+        load_raw(t.y0 - 1, w[0]);
+        load_raw(t.y0, w[1]);
+        complete(t.y0 - 1, w[0]);
+        complete(t.y0, w[1]);
+#pragma unroll
+        for (int k = 0; k < kMedChunk; ++k)
+            if (t.y0 + k + 1 <= t.y1) load_raw(t.y0 + k + 1, nw[k]);
         for (int yb = t.y0; yb < t.y1; yb += kMedChunk) {
 #pragma unroll
             for (int k = 0; k < kMedChunk; ++k)
-                if (yb + k + 1 <= t.y1) load_own(yb + k + 1, w[k + 2]);
+                if (yb + k + 1 <= t.y1) {
 #pragma unroll
-            for (int k = 0; k < kMedChunk; ++k)
-                if (yb + k + 1 <= t.y1) complete(w[k + 2]);
+                    for (int q = 0; q < 3; ++q) w[k + 2][q] = nw[k][q];
+                    complete(yb + k + 1, w[k + 2]);
+                }
             // decisions for the rows of the chunk in order; with the exact
             // Delta S a moved node is rescaled on the spot by its lane (its
             // root solves are a real call), with the quadratic one after the
@@ -646,6 +656,12 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                         if (isfinite(dc)) acc.lim += pt * pt * dc * (A(1) - rr[k] * rr[k]);
                     }
                 }
+            }
+            {
+                const int yn = yb + kMedChunk;
+#pragma unroll
+                for (int k = 0; k < kMedChunk; ++k)
+                    if (yn < t.y1 && yn + k + 1 <= t.y1) load_raw(yn + k + 1, nw[k]);
             }
             if constexpr (DS != kExact) {
                 // rescale the chunk's moved nodes kPipe rows at a time: the
