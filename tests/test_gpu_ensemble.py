@@ -58,6 +58,26 @@ def test_d2q9_periodic_single_step_fp64(limiter, kw, ds):
     assert_stats_close(pr)
 
 
+@pytest.mark.parametrize("ds", [0, 1])
+@pytest.mark.parametrize("tile", [1, 3, 5, 16])
+@pytest.mark.parametrize("limiter,kw", [(SMOOTH | RATIONAL | THRESH | 3, dict(ens_c=4.0, ens_k=1.0, delta_ens=0.02)),
+                                        (BUDGET | 2, dict(ens_c=0.9))])
+def test_tile_heights_fp64(limiter, kw, tile, ds):
+    """The second pass walks each tile's rows in short chunks and rescales a
+    chunk's moved nodes after its decisions: tiles shorter than a chunk, and
+    tiles that end inside one, give the oracle's result."""
+    L = lbm()
+    f0 = wl.random_populations(9, 300, 70, seed=23, amp=0.03, spike_frac=0.05, spike_amp=0.35)
+    dom = L.Domain(lattice=D2Q9, nx=300, ny=70, beta=0.97, qe=0, ds_form=ds, limiter=limiter,
+                   delta_trim=1e-3, delta_median=1e-5, **kw)
+    pr = Pair(dom, f0, steps=1, storage=0, tile=tile)
+    assert pr.so["n_ensemble"] > 0 and pr.so["n_filtered"] > 0
+    assert_masks_equal(pr)
+    assert_ds_close(pr, 1e-12)
+    fields_close(pr)
+    assert_stats_close(pr)
+
+
 @pytest.mark.parametrize("limiter,kw", [(THRESH, dict(ens_c=5.0)), (SMOOTH, dict(ens_k=0.5, delta_ens=0.01)),
                                         (BUDGET, dict(ens_c=0.5))])
 def test_cavity_multistep_fp64(limiter, kw):
