@@ -354,7 +354,9 @@ __device__ __forceinline__ A h_closed(A y)
 // the deviation (1 - alpha) x, so in s = alpha - 1 the equation is
 // G(s) = sum f*_i h(-s x_i) - sum f*_i h(x_i) = 0 with G convex and
 // increasing on [0, s_max], s_max the positivity boundary of f~, and
-// G(0) < 0.  Newton from the LBGK mirror s = 1, kept inside the bracket
+// G(0) < 0.  Newton from the LBGK mirror s = 1 corrected by the cubic term
+// of h (h(y) = y^2/2 - y^3/6 + O(y^4) puts the root at
+// s = 1 - sum f*_i x_i^3 / (3 sum f*_i x_i^2) + O(x^2)), kept inside the bracket
 // (bisection when a step leaves it), until G is at the rounding level of its
 // sums; the result is moved down to a point with G <= 0, so the entropy does
 // not decrease.  A root short of s_max exists iff G(s_max) >= 0; that is
@@ -367,13 +369,16 @@ __device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
 {
     constexpr A eps = sizeof(A) == 8 ? A(2.220446049250313e-16) : A(1.1920929e-7);
     const A inf = A(__builtin_huge_val());
-    A smax = inf, target = A(0);
+    A smax = inf, target = A(0), m2 = A(0), m3 = A(0);
     bool nonpos = false;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (x[i] > A(0)) smax = fmin(smax, A(1) / x[i]);
         nonpos |= x[i] <= A(-1);
         target += fs[i] * h_closed(x[i]);
+        const A fx2 = fs[i] * x[i] * x[i];
+        m2 += fx2;
+        m3 += fx2 * x[i];
     }
     posrule = false;
     if (!(smax < inf)) return A(2);        // f = f*: every alpha gives f
@@ -393,7 +398,13 @@ __device__ A elbm_alpha(const A (&fs)[Q], const A (&x)[Q], bool& posrule)
         }
         return g;
     };
-    A lo = A(0), hi = smax, s = fmin(A(1), A(0.5) * smax);
+    A s = A(1);
+    if (m2 > A(0)) {
+        const A c = m3 / (A(3) * m2);
+        if (fabs(c) < A(0.5)) s -= c;
+    }
+    A lo = A(0), hi = smax;
+    s = fmin(s, A(0.5) * smax);
     A g = A(0), dg;
     bool at_s = false;      // g = G(s)
     bool above = false;     // some G > 0 seen, or G(s_max) >= 0: a root lies in [lo, hi]
