@@ -81,6 +81,28 @@ def test_alpha_tends_to_lbgk(orc, lattice):
     assert errs[2] < 1e-3
 
 
+@pytest.mark.parametrize("lattice", [D1Q3, D2Q9])
+def test_alpha_first_correction_is_the_cubic_term(orc, lattice):
+    """Near equilibrium h(y) = y^2/2 - y^3/6 + O(y^4), so the root of
+    sum f* h((1 - alpha) x) = sum f* h(x) is alpha = 2 + e with
+    e = -sum f* x^3 / (3 sum f* x^2) + O(x^2), x = (f - f*)/f*: the residual
+    after that correction is second order in the deviation (a hundredfold
+    smaller for a tenfold smaller deviation), alpha - 2 itself first order."""
+    res, first = [], []
+    for amp in (1e-2, 1e-3):
+        f = random_state(lattice, 7, amp)
+        fs = fstar_of(orc, lattice, f)
+        x = (f - fs) / fs
+        e = -np.sum(fs * x ** 3) / (3 * np.sum(fs * x ** 2))
+        a, pr = orc.elbm_alpha(f, fs)
+        assert not pr
+        first.append(abs(a - 2.0))
+        res.append(abs(a - 2.0 - e))
+    assert res[0] < 0.1 * first[0] and res[1] < 0.01 * first[1]
+    assert 30 < res[0] / res[1] < 300          # second order
+    assert 3 < first[0] / first[1] < 30         # first order
+
+
 def test_no_root_takes_the_positivity_boundary(orc):
     """A state with one population far above f*: no state of equal entropy
     on the non-negative part of the line, so f~ stops where the first
