@@ -21,7 +21,8 @@
  * (Sec. 4.4 reading: three nodes along a neighbouring wall, self plus two inner
  * axis neighbours next to a corner) and the lid density rho0 have no closed
  * form or printed value to check against; only the vortex centres of Table 1
- * (to within a node or two) constrain them.
+ * (to within a node or two) and the left-right mirror symmetry of the step
+ * (a stencil taken on the wrong side breaks it) constrain them.
  *
  * Layout: populations f[i*n + y*nx + x], n = nx*ny, x fastest (ny = 1 for
  * D1Q3).  The state passed in and out of orc_step is the post-streaming
