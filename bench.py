@@ -306,7 +306,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--kernel-steps", type=int, default=50, help="eager steps timed per kernel for the roofline")
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity ensemble")
-    ap.add_argument("--tile-h", type=int, default=0, help="fixed rows per tile instead of autotuning")
+    ap.add_argument("--tile-h", type=int, default=0, help="rows per median/reduction tile (1..64; 0: 64)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
