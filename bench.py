@@ -97,13 +97,17 @@ def time_steps(torch, L, ctx, stream, steps, warmup):
     return e0.elapsed_time(e1)          # ms
 
 
-def cpu_baseline(wl, seconds=12.0, delta_median=1e-4):
-    """The FP64 oracle (single thread) on a 1024 x 1024 replica of the workload."""
+def cpu_baseline(wl, seconds=12.0, dom=None):
+    """The FP64 oracle (single thread) on a 1024 x 1024 replica of the workload
+    (`dom`: the timed domain, whose limiter and collision settings it copies)."""
     from oracle import oracle as orc
     n = 1024
     rho, u = wl.taylor_green(n, u0=0.05, mode=1, perturb=1e-3, seed=wl.DEFAULT_SEED)
-    p = orc.make_params(lattice=2, nx=n, ny=n, beta=wl.beta_from_nu(1e-4), qe=0, ds_form=1, limiter=3,
-                        delta_trim=1e-4, delta_median=delta_median, bc=0)
+    kw = dict(qe=0, limiter=3, delta_median=1e-4)
+    if dom is not None:
+        kw = dict(qe=dom.qe, limiter=dom.limiter, delta_median=dom.delta_median, collision=dom.collision,
+                  ens_k=dom.ens_k, delta_ens=dom.delta_ens, ens_c=dom.ens_c)
+    p = orc.make_params(lattice=2, nx=n, ny=n, beta=wl.beta_from_nu(1e-4), ds_form=1, delta_trim=1e-4, bc=0, **kw)
     f = orc.init_equilibrium(p, rho, u)
     steps = 0
     t0 = time.perf_counter()
@@ -309,6 +313,9 @@ def main():
     ap.add_argument("--tile-h", type=int, default=0, help="rows per median/reduction tile (1..64; 0: 64)")
     ap.add_argument("--delta-median", type=float, default=None,
                     help="median tolerance instead of 1e-4 (below the Delta S' of most nodes the filter acts)")
+    ap.add_argument("--workload", choices=("headline", "elbm", "smooth"), default="headline",
+                    help="elbm: entropic f*, ELBM collisions, no limiter; smooth: the headline limiters plus "
+                         "the smooth ensemble factor (k = 1/2, delta = 0.01)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
@@ -346,6 +353,12 @@ def main():
     dom = c2_domain(L, wl, n)
     dmed = 1e-4 if args.delta_median is None else args.delta_median
     dom.delta_median = dmed
+    if args.workload == "elbm":
+        dom.qe, dom.limiter, dom.collision = L.LBM_QE_ENTROPIC, L.LBM_LIM_NONE, L.LBM_COLL_ELBM
+    elif args.workload == "smooth":
+        dom.limiter |= L.LBM_LIM_ENS_SMOOTH
+        dom.ens_k, dom.delta_ens = 0.5, 0.01
+    default = args.workload == "headline" and dmed == 1e-4
     print(f"[bench] creating {n}x{n} FP32 context", file=sys.stderr, flush=True)
     run = L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)
     if args.tile_h:
@@ -364,9 +377,14 @@ def main():
     achieved = alg_bytes / (k1_ms * 1e-3) / 1e9
     step_achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     # the recorded traffic belongs to the default tolerance (no wave stores Delta S')
-    traffic = load_traffic() if dmed == 1e-4 else None
+    traffic = load_traffic() if default else None
     limiters = ("trimming + 3x3 median limiter (delta=1e-4)" if dmed == 1e-4 else
                 f"trimming (delta=1e-4) + 3x3 median limiter (delta={dmed:g})")
+    if args.workload == "smooth":
+        limiters += " + smooth ensemble factor (k=0.5, delta=0.01)"
+    elif args.workload == "elbm":
+        limiters = "ELBM collisions, no limiter"
+    feq = "entropic f*" if args.workload == "elbm" else "polynomial f*"
     out = {
         "metric": "MLUPS + % HBM roofline, limited D2Q9 step; batched/low-precision vs plain FP32",
         "value": round(mlups, 1),
@@ -382,7 +400,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"D2Q9 periodic Taylor-Green + random-phase perturbation {n}x{n}, FP32 shifted SoA, "
-                        f"nu=1e-4, {limiters}, polynomial f*, quadratic dS, "
+                        f"nu=1e-4, {limiters}, {feq}, quadratic dS, "
                         "per-workgroup partials every step, FP64 global stats of the last step",
             "nx": n, "ny": n, "storage": "f32_shift", "tile": list(tile), "graph_chunk": 64,
         },
@@ -399,13 +417,20 @@ def main():
                   "max_dS": stats["max_dS"], "n_nonfinite": stats["n_nonfinite"]},
     }
     ctx.close()
+    if not default:
+        # the roofline object is defined for the headline's collision kernel;
+        # these workloads are reported by kernel time only
+        if args.workload == "elbm":
+            out["kernels"]["dominant"] = "k_collide2d<float, 1, 1, 0, true>"
+        out["roofline"] = None
+        out["note"] = "not the headline workload: kernel times only (no roofline, no traffic record)"
     if args.calibrate_copy:
         out["copy_calibration"] = copy_calibration(torch, stream)
     if args.variants:
         out["variants"] = variants(torch, L, wl, stream, args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, dmed)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, dom)
     print(json.dumps(out), flush=True)
 
 
