@@ -122,6 +122,20 @@ def cpu_baseline(wl, seconds=12.0, dom=None):
                       f"limiters, quadratic dS), {el:.1f} s"}
 
 
+def workload_text(n, workload="headline", delta_median=1e-4):
+    """The `config.workload` description of the timed run."""
+    limiters = ("trimming + 3x3 median limiter (delta=1e-4)" if delta_median == 1e-4 else
+                f"trimming (delta=1e-4) + 3x3 median limiter (delta={delta_median:g})")
+    if workload == "smooth":
+        limiters += " + smooth ensemble factor (k=0.5, delta=0.01)"
+    elif workload == "elbm":
+        limiters = "ELBM collisions, no limiter"
+    feq = "entropic f*" if workload == "elbm" else "polynomial f*"
+    return (f"D2Q9 periodic Taylor-Green + random-phase perturbation {n}x{n}, FP32 shifted SoA, "
+            f"nu=1e-4, {limiters}, {feq}, quadratic dS, "
+            "per-workgroup partials every step, FP64 global stats of the last step")
+
+
 def load_traffic():
     """HBM bytes per launch of the dominant kernel from the committed PMC
     record, or None when the kernel sources changed since it was taken."""
@@ -378,13 +392,6 @@ def main():
     step_achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     # the recorded traffic belongs to the default tolerance (no wave stores Delta S')
     traffic = load_traffic() if default else None
-    limiters = ("trimming + 3x3 median limiter (delta=1e-4)" if dmed == 1e-4 else
-                f"trimming (delta=1e-4) + 3x3 median limiter (delta={dmed:g})")
-    if args.workload == "smooth":
-        limiters += " + smooth ensemble factor (k=0.5, delta=0.01)"
-    elif args.workload == "elbm":
-        limiters = "ELBM collisions, no limiter"
-    feq = "entropic f*" if args.workload == "elbm" else "polynomial f*"
     out = {
         "metric": "MLUPS + % HBM roofline, limited D2Q9 step; batched/low-precision vs plain FP32",
         "value": round(mlups, 1),
@@ -399,9 +406,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"D2Q9 periodic Taylor-Green + random-phase perturbation {n}x{n}, FP32 shifted SoA, "
-                        f"nu=1e-4, {limiters}, {feq}, quadratic dS, "
-                        "per-workgroup partials every step, FP64 global stats of the last step",
+            "workload": workload_text(n, args.workload, dmed),
             "nx": n, "ny": n, "storage": "f32_shift", "tile": list(tile), "graph_chunk": 64,
         },
         "roofline": {

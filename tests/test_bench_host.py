@@ -88,3 +88,14 @@ def test_counter_summary_needs_the_calibration_kernel(tmp_path, monkeypatch):
     with pytest.raises(SystemExit):
         bench.summarize_pmc(str(f), str(w))
     assert not (tmp_path / "traffic.json").exists()
+
+
+def test_workload_text():
+    # the headline description, as the benchmark has always reported it
+    assert bench.workload_text(4096) == (
+        "D2Q9 periodic Taylor-Green + random-phase perturbation 4096x4096, FP32 shifted SoA, nu=1e-4, "
+        "trimming + 3x3 median limiter (delta=1e-4), polynomial f*, quadratic dS, per-workgroup partials "
+        "every step, FP64 global stats of the last step")
+    assert "median limiter (delta=0)" in bench.workload_text(4096, delta_median=0.0)
+    assert "ELBM collisions, no limiter, entropic f*" in bench.workload_text(4096, "elbm")
+    assert "smooth ensemble factor (k=0.5, delta=0.01), polynomial f*" in bench.workload_text(4096, "smooth")
