@@ -17,12 +17,15 @@
  *   - median entropy filter: Sec. 3.5, cavity stencil rule of Sec. 4.4
  *   - free flight: Sec. 2; bounce-back walls and constant lid: Sec. 4.4.1
  *
- * Parity unpinned: the near-wall and corner median stencils of the cavity
- * (Sec. 4.4 reading: three nodes along a neighbouring wall, self plus two inner
- * axis neighbours next to a corner) and the lid density rho0 have no closed
- * form or printed value to check against; only the vortex centres of Table 1
- * (to within a node or two) and the left-right mirror symmetry of the step
- * (a stencil taken on the wrong side breaks it) constrain them.
+ * The median step (stencils with their periodic wrap, the FLOOR / GATE
+ * decision on the post-collision Delta S, the landing on the target) is
+ * checked against an independent restatement in the tests, and planted
+ * mistakes in copies of this file are shown to fail those checks.  Still a
+ * reading of the paper, with no printed value to check it against: which
+ * nodes form the near-wall and corner stencils of the cavity (Sec. 4.4: three
+ * nodes along a neighbouring wall, self plus two inner axis neighbours next
+ * to a corner) and the lid density rho0; only the vortex centres of Table 1
+ * (to within a node or two) constrain that reading.
  *
  * Layout: populations f[i*n + y*nx + x], n = nx*ny, x fastest (ny = 1 for
  * D1Q3).  The state passed in and out of orc_step is the post-streaming
