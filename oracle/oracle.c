@@ -1,10 +1,14 @@
 /*
  * oracle.c -- plain FP64 CPU reference of the limited lattice Boltzmann step.
  *
- * TEST INFRASTRUCTURE ONLY (see oracle.h).  Sequential loops in row-major
- * node order, no blocking or fusion: each function follows one formula of
- * Brownlee, Gorban & Levesley (arXiv:0704.0043) so that it can be checked
- * against the paper by eye.  Built with -O2 -ffp-contract=off.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Loops in row-major node order,
+ * no blocking or fusion: each function follows one formula of Brownlee,
+ * Gorban & Levesley (arXiv:0704.0043) so that it can be checked against the
+ * paper by eye.  Built with -O2 -ffp-contract=off.  The per-node loops carry
+ * OpenMP pragmas: the build the tests use ignores them (no -fopenmp); a
+ * separate build that only times the CPU baseline honours them.  The global
+ * sums are formed afterwards from per-node terms in row-major order, so both
+ * builds give the same bits.
  *
  * Readings of points where the paper is silent or garbled:
  *   - D1Q3 entropic f*: the printed left/right movers contradict the velocity
@@ -26,6 +30,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---- lattices (Sec. 4.1) ------------------------------------------------ */
 
@@ -43,6 +50,16 @@ static const int D2_OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 static const double D2_W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
                                1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* threads the per-node loops run on (1 unless built with OpenMP) */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int orc_q(int32_t lattice)
 {
@@ -376,6 +393,7 @@ int orc_stream(const orc_params* p, const double* o, double* f)
 {
     if (check_params(p)) return -1;
     int q = orc_q(p->lattice), nx = p->nx, ny = p->ny, n = nx * ny;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
             for (int i = 0; i < q; ++i) {
@@ -504,8 +522,19 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
     double* dpre = (double*)malloc(sizeof(double) * n);
     double* dpost = (double*)malloc(sizeof(double) * n);
     uint8_t* m = (uint8_t*)calloc(n, 1);
-    if (!fst || !fpost || !o || !dpre || !dpost || !m) {
+    /* per-node terms of the global sums, summed in row-major order after
+     * each pass (the per-node loops are then independent of each other) */
+    double* srho = (double*)malloc(sizeof(double) * n);
+    double* sjx = (double*)malloc(sizeof(double) * n);
+    double* sjy = (double*)malloc(sizeof(double) * n);
+    double* sent = (double*)malloc(sizeof(double) * n);
+    double* slim = (double*)malloc(sizeof(double) * n);
+    uint8_t* npos = (uint8_t*)calloc(n, 1);     /* positivity rule acted (0..2 times) */
+    uint8_t* limon = (uint8_t*)calloc(n, 1);    /* slim holds a term */
+    if (!fst || !fpost || !o || !dpre || !dpost || !m || !srho || !sjx || !sjy || !sent || !slim || !npos ||
+        !limon) {
         free(fst); free(fpost); free(o); free(dpre); free(dpost); free(m);
+        free(srho); free(sjx); free(sjy); free(sent); free(slim); free(npos); free(limon);
         return -2;
     }
 
@@ -516,6 +545,7 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
     s.total_entropy = p->entropy ? 0.0 : NAN;
 
     /* pass 1: moments, collision, Delta S of every node */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int site = y * nx + x;
@@ -529,10 +559,10 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 jx += vx * fl[i];
                 jy += vy * fl[i];
             }
-            s.mass += rho;
-            s.mom_x += jx;
-            s.mom_y += jy;
-            if (!isfinite(rho) || !isfinite(jx) || !isfinite(jy)) s.n_nonfinite++;
+            srho[site] = rho;
+            sjx[site] = jx;
+            sjy[site] = jy;
+            sent[site] = NAN;
             dpre[site] = 0.0;
             dpost[site] = 0.0;
             int type = node_type(p, x, y);
@@ -554,7 +584,6 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 m[site] = ORC_MASK_NOTFLUID;
                 continue;
             }
-            s.n_fluid++;
             double ux = jx / rho, uy = jy / rho;   /* eq. (macro_dis) */
             orc_equilibrium(p->lattice, p->qe, rho, ux, uy, fs);
             if (p->collision == ORC_COLL_ELBM) {
@@ -564,7 +593,7 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 for (int i = 0; i < q; ++i) fp[i] = fl[i] + alpha * p->beta * (fs[i] - fl[i]);
                 if (pr) {
                     m[site] |= ORC_MASK_POSITIVITY;
-                    s.n_positivity++;
+                    npos[site]++;
                 }
             } else {
                 for (int i = 0; i < q; ++i)      /* eq. (collLBGK) */
@@ -576,10 +605,17 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 fst[i * n + site] = fs[i];
                 fpost[i * n + site] = fp[i];
             }
-            if (p->entropy) {
-                double e = orc_entropy(p->lattice, fl);
-                if (isfinite(e)) s.total_entropy += e;
-            }
+            if (p->entropy) sent[site] = orc_entropy(p->lattice, fl);
+        }
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int site = y * nx + x;
+            s.mass += srho[site];
+            s.mom_x += sjx[site];
+            s.mom_y += sjy[site];
+            if (!isfinite(srho[site]) || !isfinite(sjx[site]) || !isfinite(sjy[site])) s.n_nonfinite++;
+            if (node_type(p, x, y) == NODE_FLUID) s.n_fluid++;
+            if (isfinite(sent[site])) s.total_entropy += sent[site];
         }
 
     /* ensemble quantities of the post-collision Delta S (Sec. 3.3, 3.4):
@@ -635,22 +671,14 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
     }
 
     /* pass 2: limiter on the post-collision state */
-    double max_ds = 0.0;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int site = y * nx + x;
             if (node_type(p, x, y) != NODE_FLUID) continue;
             double d = dpost[site];
             double dp = dpre[site];
-            if (isinf(d) || isinf(dp)) {
-                s.n_nonpositive++;
-                m[site] |= ORC_MASK_NONPOS;
-            }
-            if (isfinite(dp)) s.sum_dS_pre += dp;
-            if (isfinite(d)) {
-                s.sum_dS_post += d;
-                if (d > max_ds) max_ds = d;
-            }
+            if (isinf(d) || isinf(dp)) m[site] |= ORC_MASK_NONPOS;
             double phi = 1.0;
             double fpn[9], fsn[9];              /* f' and f* of this node */
             for (int i = 0; i < q; ++i) {
@@ -666,7 +694,6 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                                     ? 0.0
                                     : homothety_phi(p, q, fpn, fsn, d, t);
                     if (pt < phi) phi = pt;
-                    s.n_trimmed++;
                 }
             }
             if (p->limiter & ORC_LIM_MEDIAN) {
@@ -689,7 +716,6 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                         m[site] |= ORC_MASK_MEDIAN;
                         double pm = homothety_phi(p, q, fpn, fsn, d, t);
                         if (pm < phi) phi = pm;
-                        s.n_filtered++;
                     }
                 }
             }
@@ -721,7 +747,6 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 }
                 if (pe < 1.0) {
                     m[site] |= ORC_MASK_ENSEMBLE;
-                    s.n_ensemble++;
                     if (pe < phi) phi = pe;
                 }
             }
@@ -740,7 +765,7 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 }
                 if (pp < 1.0) {
                     m[site] |= ORC_MASK_POSITIVITY;
-                    s.n_positivity++;
+                    npos[site]++;
                     if (pp < phi) phi = pp;
                 }
             }
@@ -751,8 +776,29 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
                 o[i * n + site] = fl[i];
             }
             const double after = phi < 1.0 ? orc_delta_s(q, p->ds_form, fl, fs) : d;
-            if (phi < 1.0 && isfinite(d)) s.limiter_production += d - after;
+            if (phi < 1.0 && isfinite(d)) {
+                slim[site] = d - after;
+                limon[site] = 1;
+            }
             if (dS_lim) dS_lim[site] = after;
+        }
+    double max_ds = 0.0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int site = y * nx + x;
+            s.n_positivity += npos[site];
+            if (node_type(p, x, y) != NODE_FLUID) continue;
+            const double d = dpost[site], dp = dpre[site];
+            if (m[site] & ORC_MASK_NONPOS) s.n_nonpositive++;
+            if (isfinite(dp)) s.sum_dS_pre += dp;
+            if (isfinite(d)) {
+                s.sum_dS_post += d;
+                if (d > max_ds) max_ds = d;
+            }
+            if (m[site] & ORC_MASK_TRIM) s.n_trimmed++;
+            if (m[site] & ORC_MASK_MEDIAN) s.n_filtered++;
+            if (m[site] & ORC_MASK_ENSEMBLE) s.n_ensemble++;
+            if (limon[site]) s.limiter_production += slim[site];
         }
     s.max_dS = max_ds;
     s.lbgk_production = (1.0 - c * c) * s.sum_dS_pre;
@@ -767,5 +813,6 @@ int orc_step(const orc_params* p, double* f, orc_stats* st, uint8_t* mask,
     if (mask) memcpy(mask, m, n);
     if (dS) memcpy(dS, dpost, sizeof(double) * n);
     free(fst); free(fpost); free(o); free(dpre); free(dpost); free(m);
+    free(srho); free(sjx); free(sjy); free(sent); free(slim); free(npos); free(limon);
     return 0;
 }

@@ -98,6 +98,9 @@ typedef struct {
     int64_t n_positivity;   /* nodes where the positivity rule acted (limiter, or ELBM without a root) */
 } orc_stats;
 
+/* threads the per-node loops of orc_step run on (1 unless built with OpenMP,
+ * which only the CPU-baseline timing build is) */
+int    orc_threads(void);
 int    orc_q(int32_t lattice);
 /* velocity components and entropy weights W_i of the paper's lattices */
 void   orc_velocity(int32_t lattice, int32_t i, int32_t* vx, int32_t* vy);

@@ -16,6 +16,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the same source built with OpenMP: used only to time the CPU baseline
+TIMING_LIB_PATH = os.path.join(HERE, "liboracle_omp.so")
 
 D1Q3, D2Q9 = 1, 2
 QE_POLY, QE_ENTROPIC = 0, 1
@@ -60,43 +62,73 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+def _stale(path, src):
+    return not os.path.exists(path) or os.path.getmtime(path) < max(
+        os.path.getmtime(src), os.path.getmtime(os.path.join(HERE, "oracle.h")))
+
+
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain -O2, no FP contraction)."""
     src = os.path.join(HERE, "oracle.c")
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+    if force or _stale(LIB_PATH, src):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
                "-o", LIB_PATH, src, "-lm"]
         subprocess.run(cmd, check=True)
     return LIB_PATH
 
 
+def build_timing(force: bool = False) -> str:
+    """The same source with -fopenmp (per-node loops over rows in parallel,
+    global sums still in row-major order): the CPU baseline's timing build."""
+    src = os.path.join(HERE, "oracle.c")
+    if force or _stale(TIMING_LIB_PATH, src):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+               "-o", TIMING_LIB_PATH, src, "-lm"]
+        subprocess.run(cmd, check=True)
+    return TIMING_LIB_PATH
+
+
 _lib = None
+_timing_lib = None
+
+
+def _declare(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_threads.restype = ctypes.c_int
+    L.orc_q.argtypes = [ctypes.c_int32]
+    L.orc_equilibrium.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, dp]
+    L.orc_delta_s.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp]
+    L.orc_delta_s.restype = ctypes.c_double
+    L.orc_h.argtypes = [ctypes.c_double]
+    L.orc_h.restype = ctypes.c_double
+    L.orc_entropy.argtypes = [ctypes.c_int32, dp]
+    L.orc_entropy.restype = ctypes.c_double
+    L.orc_median.argtypes = [dp, ctypes.c_int32]
+    L.orc_median.restype = ctypes.c_double
+    L.orc_elbm_alpha.argtypes = [ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_int32)]
+    L.orc_elbm_alpha.restype = ctypes.c_double
+    L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Stats),
+                           ctypes.POINTER(ctypes.c_uint8), dp, dp]
+    L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
+    L.orc_init_equilibrium.argtypes = [ctypes.POINTER(Params), dp, dp, dp]
+    return L
+
+
+def timing_lib():
+    """ctypes handle of the OpenMP timing build (CPU baseline only)."""
+    global _timing_lib
+    if _timing_lib is None:
+        build_timing()
+        _timing_lib = _declare(ctypes.CDLL(TIMING_LIB_PATH))
+    return _timing_lib
 
 
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_q.argtypes = [ctypes.c_int32]
-        L.orc_equilibrium.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_double, dp]
-        L.orc_delta_s.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp]
-        L.orc_delta_s.restype = ctypes.c_double
-        L.orc_h.argtypes = [ctypes.c_double]
-        L.orc_h.restype = ctypes.c_double
-        L.orc_entropy.argtypes = [ctypes.c_int32, dp]
-        L.orc_entropy.restype = ctypes.c_double
-        L.orc_median.argtypes = [dp, ctypes.c_int32]
-        L.orc_median.restype = ctypes.c_double
-        L.orc_elbm_alpha.argtypes = [ctypes.c_int32, dp, dp, ctypes.POINTER(ctypes.c_int32)]
-        L.orc_elbm_alpha.restype = ctypes.c_double
-        L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Stats),
-                               ctypes.POINTER(ctypes.c_uint8), dp, dp]
-        L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
-        L.orc_init_equilibrium.argtypes = [ctypes.POINTER(Params), dp, dp, dp]
-        _lib = L
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
 
 
@@ -182,17 +214,19 @@ def init_equilibrium(p: Params, rho: np.ndarray, u: np.ndarray) -> np.ndarray:
     return f.reshape(q_of(p.lattice), p.ny, p.nx)
 
 
-def step(p: Params, f: np.ndarray, steps: int = 1, record: bool = False, record_lim: bool = False):
+def step(p: Params, f: np.ndarray, steps: int = 1, record: bool = False, record_lim: bool = False,
+         handle=None):
     """Advance f in place by `steps` steps; returns (stats of the last step,
     mask, dS) with mask/dS of the last step when `record` is set, and also
-    the Delta S of the limited states when `record_lim` is set."""
+    the Delta S of the limited states when `record_lim` is set.  `handle`
+    selects another build of the same source (the timing build)."""
     assert f.dtype == np.float64 and f.flags.c_contiguous
     n = p.nx * p.ny
     st = Stats()
     mask = np.zeros(n, dtype=np.uint8) if record else None
     ds = np.zeros(n) if record else None
     dsl = np.zeros(n) if record_lim else None
-    L = lib()
+    L = handle if handle is not None else lib()
     for k in range(steps):
         last = k == steps - 1
         mptr = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if (record and last) else None
