@@ -6,15 +6,19 @@ entropy trimming and the 3x3 median filter both on (delta = 1e-4),
 polynomial f*, quadratic Delta S.  One step = the collision kernel (free
 flight, moments, f*, over-relaxation, Delta S', trimming, store, one partial
 of the reduction terms per workgroup) plus the median kernel (3x3 median of
-Delta S', the filtered nodes rescaled in place); steps run as captured HIP
-graphs, and the FP64 global stats of the last step are formed inside the
-timed region.
+Delta S', the filtered nodes rescaled in place); every step runs inside
+captured HIP graphs (chunks of 64 steps and the powers of two below, captured
+when the context is created), and the FP64 global stats of the last step are
+formed inside the timed region.
 
-Prints one JSON line: MLUPS of the whole job, the roofline of the dominant
+Prints one JSON line: MLUPS of the whole job; the roofline of the dominant
 kernel (the collision kernel: algorithmic bytes of the step divided by that
-kernel's average duration, measured with HIP events on its stream), the
-roofline of the whole step, and the FP64 CPU oracle timed on the host on a
-1024 x 1024 replica of the same workload.
+kernel's average duration, measured with HIP events on its stream once the
+clocks have settled); the roofline of the whole step; the same step with the
+median filter moving a few percent of the nodes (delta_median = 1e-9); the
+max-norm error of a 1024 x 1024 replica against the FP64 CPU oracle; and that
+oracle timed on the host on the replica (its OpenMP build on the host's cores,
+and one thread).
 
 --variants adds the reduced-precision runs (FP16 / BF16 shifted storage on
 an 8192 x 8192 double shear layer, against FP32 on the same input), the
@@ -97,29 +101,87 @@ def time_steps(torch, L, ctx, stream, steps, warmup):
     return e0.elapsed_time(e1)          # ms
 
 
-def cpu_baseline(wl, seconds=12.0, dom=None):
-    """The FP64 oracle (single thread) on a 1024 x 1024 replica of the workload
-    (`dom`: the timed domain, whose limiter and collision settings it copies)."""
-    from oracle import oracle as orc
-    n = 1024
+REPLICA_N = 1024
+
+
+def replica_params(orc, wl, dom, n=REPLICA_N):
+    """Oracle parameters of an n x n replica of the timed domain (same nu,
+    U0, mode, perturbation, limiters and Delta S form) and its initial fields."""
     rho, u = wl.taylor_green(n, u0=0.05, mode=1, perturb=1e-3, seed=wl.DEFAULT_SEED)
-    kw = dict(qe=0, limiter=3, delta_median=1e-4)
-    if dom is not None:
-        kw = dict(qe=dom.qe, limiter=dom.limiter, delta_median=dom.delta_median, collision=dom.collision,
-                  ens_k=dom.ens_k, delta_ens=dom.delta_ens, ens_c=dom.ens_c)
-    p = orc.make_params(lattice=2, nx=n, ny=n, beta=wl.beta_from_nu(1e-4), ds_form=1, delta_trim=1e-4, bc=0, **kw)
-    f = orc.init_equilibrium(p, rho, u)
-    steps = 0
+    p = orc.make_params(lattice=2, nx=n, ny=n, beta=dom.beta, ds_form=dom.ds_form, bc=0, qe=dom.qe,
+                        limiter=dom.limiter, delta_trim=dom.delta_trim, delta_median=dom.delta_median,
+                        collision=dom.collision, ens_k=dom.ens_k, delta_ens=dom.delta_ens, ens_c=dom.ens_c)
+    return p, rho, u
+
+
+def run_oracle_for(orc, p, f, seconds, handle=None, max_steps=2000):
+    """Step the oracle one step at a time until `seconds` have passed; every
+    step records its mask and Delta S' (kept for the last).  Returns
+    (steps, elapsed, (stats, mask, dS) of the last step)."""
+    steps, el, rec = 0, 0.0, None
     t0 = time.perf_counter()
-    while True:
-        orc.step(p, f, 1)
+    while steps < max_steps and el < seconds:
         steps += 1
+        rec = orc.step(p, f, 1, record=True, handle=handle)
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 1000:
-            break
-    return {"value": round(n * n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 C oracle, single thread, {steps} steps of a {n}x{n} replica (same nu, U0, mode, "
-                      f"limiters, quadratic dS), {el:.1f} s"}
+    return steps, el, rec
+
+
+def cpu_baseline(wl, seconds=24.0, dom=None):
+    """The FP64 oracle on a 1024 x 1024 replica of the timed workload, timed
+    on the host: its plain build on one thread for half of `seconds`, then its
+    OpenMP build (per-node loops over rows, on the host's cores) for the other
+    half.  Returns the baseline record and the OpenMP leg's final state (for
+    the error statement of the GPU replica)."""
+    from oracle import oracle as orc
+    n = REPLICA_N
+    p, rho, u = replica_params(orc, wl, dom, n)
+    f1 = orc.init_equilibrium(p, rho, u)
+    s1, e1, _ = run_oracle_for(orc, p, f1, seconds / 2)
+    handle = orc.timing_lib()
+    threads = int(handle.orc_threads())
+    f2 = orc.init_equilibrium(p, rho, u)
+    s2, e2, rec = run_oracle_for(orc, p, f2, seconds / 2, handle=handle)
+    single = round(n * n * s1 / e1 / 1e6, 3)
+    multi = round(n * n * s2 / e2 / 1e6, 3)
+    base = {"value": multi, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "per_core": round(multi / threads, 3), "single_thread": single,
+            "host_cpus_allowed": len(os.sched_getaffinity(0)),
+            "sample": f"FP64 C oracle on a {n}x{n} replica of the timed workload (same nu, U0, mode, perturbation, "
+                      f"limiters, dS form): OpenMP build on {threads} threads, {s2} steps in {e2:.1f} s; plain "
+                      f"build on one thread, {s1} steps in {e1:.1f} s (a baseline only)"}
+    return base, (s2, f2, rec)
+
+
+def replica_error(L, stream, dom, wl, oracle_run):
+    """Max-norm error of the GPU step (FP32 storage) against the FP64 oracle
+    on the 1024 x 1024 replica after the oracle's own number of steps:
+    rho / rho0, u / max|u_oracle|, Delta S' of the last step / its largest
+    oracle value, and the limiter masks of that step."""
+    import numpy as np
+    steps, f_o, (st_o, mask_o, ds_o) = oracle_run
+    n = REPLICA_N
+    rho_i, u_i = wl.taylor_green(n, u0=0.05, mode=1, perturb=1e-3, seed=wl.DEFAULT_SEED)
+    d = L.Domain(lattice=L.LBM_D2Q9, nx=n, ny=n, beta=dom.beta, qe=dom.qe, limiter=dom.limiter,
+                 ds_form=dom.ds_form, bc=L.LBM_BC_PERIODIC, delta_trim=dom.delta_trim,
+                 delta_median=dom.delta_median, rho0=1.0, collision=dom.collision, ens_c=dom.ens_c,
+                 ens_k=dom.ens_k, delta_ens=dom.delta_ens, rho_init=rho_i, u_init=u_i)
+    with L.lbm_create([d], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, flags=L.LBM_RUN_RECORD)) as ctx:
+        L.lbm_step(ctx, steps)
+        rho, u = L.lbm_moments(ctx)
+        mask, ds = L.lbm_limiter_mask(ctx)
+    vx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    vy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    r_o = f_o.sum(axis=0)
+    ux_o = np.tensordot(vx, f_o, axes=1) / r_o
+    uy_o = np.tensordot(vy, f_o, axes=1) / r_o
+    umax = max(np.abs(ux_o).max(), np.abs(uy_o).max())
+    dsmax = float(np.abs(ds_o).max())
+    return {"replica": f"{n}x{n}", "steps": steps, "storage": "f32_shift",
+            "rho_rel": float(np.abs(rho - r_o).max() / 1.0),
+            "u_rel": float(max(np.abs(u[0] - ux_o).max(), np.abs(u[1] - uy_o).max()) / umax),
+            "dS_rel": float(np.abs(ds - ds_o).max() / dsmax) if dsmax > 0 else 0.0,
+            "mask_mismatches": int((mask != mask_o).sum()), "oracle_max_dS": dsmax, "gate_rho_u": 1e-5}
 
 
 def workload_text(n, workload="headline", delta_median=1e-4):
@@ -134,6 +196,38 @@ def workload_text(n, workload="headline", delta_median=1e-4):
     return (f"D2Q9 periodic Taylor-Green + random-phase perturbation {n}x{n}, FP32 shifted SoA, "
             f"nu=1e-4, {limiters}, {feq}, quadratic dS, "
             "per-workgroup partials every step, FP64 global stats of the last step")
+
+
+def kernel_times_warm(L, ctx, steps=50, warm_seconds=0.5):
+    """Average collision and second-pass kernel durations (ms) over `steps`
+    eager steps with HIP events on the context's stream, after graph steps
+    have kept the GPU busy for at least `warm_seconds` (clocks settled)."""
+    t0 = time.perf_counter()
+    warm = 0
+    while time.perf_counter() - t0 < warm_seconds:
+        L.lbm_step(ctx, 256)
+        L.lbm_synchronize(ctx)
+        warm += 256
+    k1, k2 = L.lbm_kernel_times(ctx, steps)
+    return k1, k2, {"warmup_graph_steps": warm, "warmup_s": round(time.perf_counter() - t0, 3),
+                    "timed_steps": steps, "mode": "eager launches, HIP events on the context stream"}
+
+
+def median_active(torch, L, wl, stream, n, steps=200):
+    """The headline step with the median tolerance below the Delta S' of most
+    nodes (delta_median = 1e-9): the filter moves a few percent of the nodes
+    every step, so the second pass rescales stored states."""
+    dom = c2_domain(L, wl, n)
+    dom.delta_median = 1e-9
+    with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream)) as ctx:
+        ms = time_steps(torch, L, ctx, stream, steps, 16)
+        st = L.lbm_entropy_stats(ctx)
+        k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
+    sites = n * n
+    return {"delta_median": 1e-9, "mlups": round(sites * steps / (ms * 1e3), 1),
+            "ms_per_step": round(ms / steps, 5), "steps": steps, "collide_ms": round(k1, 5),
+            "median_ms": round(k2, 5), "filtered_fraction": round(st["n_filtered"] / sites, 4),
+            "step_hbm_frac": round(72 * sites / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def load_traffic():
@@ -171,7 +265,7 @@ def variants(torch, L, wl, stream, args):
         dom = shear_domain(L, wl)
         with L.lbm_create([dom], L.Run(storage=storage, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
             ms = time_steps(torch, L, ctx, stream, steps, 16)
-            k1, k2 = L.lbm_kernel_times(ctx, 20)
+            k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
         sites = dom.nx * dom.ny
         b = BYTES_PER_SITE[storage] * sites
         shear[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
@@ -192,7 +286,7 @@ def variants(torch, L, wl, stream, args):
         with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
             ms = time_steps(torch, L, ctx, stream, steps, 16)
             st = L.lbm_entropy_stats(ctx)
-            k1, k2 = L.lbm_kernel_times(ctx, 20)
+            k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
         sites = dom.nx * dom.ny
         act[f"delta_median={dmed:g}"] = {
             "mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
@@ -216,7 +310,7 @@ def variants(torch, L, wl, stream, args):
         with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
             ms = time_steps(torch, L, ctx, stream, steps, 16)
             st = L.lbm_entropy_stats(ctx)
-            k1, k2 = L.lbm_kernel_times(ctx, 20)
+            k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
         sites = dom.nx * dom.ny
         ens[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
                      "collide_ms": round(k1, 5), "rest_ms": round(k2, 5),
@@ -234,7 +328,7 @@ def variants(torch, L, wl, stream, args):
         with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
             ms = time_steps(torch, L, ctx, stream, steps, 16)
             st = L.lbm_entropy_stats(ctx)
-            k1, _ = L.lbm_kernel_times(ctx, 20)
+            k1, _, _ = kernel_times_warm(L, ctx, 20, 0.2)
         sites = dom.nx * dom.ny
         coll[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
                       "collide_ms": round(k1, 5), "n_positivity": st["n_positivity"], "steps": steps}
@@ -321,8 +415,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="host seconds for the oracle (half on one thread, half on the OpenMP build)")
     ap.add_argument("--kernel-steps", type=int, default=50, help="eager steps timed per kernel for the roofline")
+    ap.add_argument("--kernel-warmup", type=float, default=0.5,
+                    help="seconds of graph steps before the per-kernel timing (clocks settle)")
+    ap.add_argument("--no-active", action="store_true", help="skip the active-median companion run")
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity ensemble")
     ap.add_argument("--tile-h", type=int, default=0, help="rows per median/reduction tile (1..64; 0: 64)")
     ap.add_argument("--delta-median", type=float, default=None,
@@ -381,9 +479,10 @@ def main():
     tile = L.lbm_tile_config(ctx)
     print(f"[bench] tile {tile}; warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
     ms = time_steps(torch, L, ctx, stream, args.steps, args.warmup)
-    print(f"[bench] per-kernel timing over {args.kernel_steps} eager steps", file=sys.stderr, flush=True)
-    k1_ms, k2_ms = L.lbm_kernel_times(ctx, args.kernel_steps)
     stats = L.lbm_entropy_stats(ctx)
+    print(f"[bench] per-kernel timing over {args.kernel_steps} eager steps after {args.kernel_warmup} s of "
+          "graph steps", file=sys.stderr, flush=True)
+    k1_ms, k2_ms, ktiming = kernel_times_warm(L, ctx, args.kernel_steps, args.kernel_warmup)
     sites = n * n
     ms_step = ms / args.steps
     mlups = sites * args.steps / (ms * 1e3)
@@ -407,7 +506,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": workload_text(n, args.workload, dmed),
-            "nx": n, "ny": n, "storage": "f32_shift", "tile": list(tile), "graph_chunk": 64,
+            "nx": n, "ny": n, "storage": "f32_shift", "tile": list(tile),
+            "graphs": "every step inside captured HIP graphs (64-step chunks and powers of two below)",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -415,7 +515,7 @@ def main():
             "traffic": traffic,
         },
         "kernels": {"dominant": DOMINANT, "collide_ms": round(k1_ms, 5), "median_ms": round(k2_ms, 5),
-                    "algorithmic_bytes_per_launch": alg_bytes},
+                    "algorithmic_bytes_per_launch": alg_bytes, "timing": ktiming},
         "step_roofline": {"achieved": round(step_achieved, 1), "frac": round(step_achieved / HBM_PEAK_GBS, 4),
                           "unit": "GB/s"},
         "stats": {"mass": stats["mass"], "n_trimmed": stats["n_trimmed"], "n_filtered": stats["n_filtered"],
@@ -429,13 +529,20 @@ def main():
             out["kernels"]["dominant"] = "k_collide2d<float, 1, 1, 0, true>"
         out["roofline"] = None
         out["note"] = "not the headline workload: kernel times only (no roofline, no traffic record)"
+    if default and not args.no_active:
+        print("[bench] the same step with the median filter acting (delta_median = 1e-9)", file=sys.stderr,
+              flush=True)
+        out["median_active"] = median_active(torch, L, wl, stream, n)
     if args.calibrate_copy:
         out["copy_calibration"] = copy_calibration(torch, stream)
     if args.variants:
         out["variants"] = variants(torch, L, wl, stream, args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, dom)
+        base, orun = cpu_baseline(wl, args.cpu_seconds, dom)
+        out["cpu_baseline"] = base
+        print(f"[bench] GPU replica against the oracle ({orun[0]} steps)", file=sys.stderr, flush=True)
+        out["error"] = replica_error(L, stream, dom, wl, orun)
     print(json.dumps(out), flush=True)
 
 

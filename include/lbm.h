@@ -129,7 +129,7 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT =
 /* run flags */
 #define LBM_RUN_RECORD 1u    /* keep per-node mask and Delta S' of every step */
 #define LBM_RUN_ENTROPY 2u   /* also accumulate sum S(f) (Sec. 4.3.1) */
-#define LBM_RUN_NO_GRAPH 4u  /* launch steps one by one (no hipGraph) */
+#define LBM_RUN_NO_GRAPH 4u  /* launch steps one by one (no captured graphs) */
 #define LBM_RUN_NO_TUNE 8u   /* accepted; the step kernels have a fixed shape */
 
 /* One simulation domain.  All domains of one context share lattice, qe,
@@ -181,7 +181,10 @@ typedef struct {
     int32_t tile_h;             /* rows per D2Q9 median/reduction tile (1..64); 0 = 64 */
     uint32_t flags;             /* LBM_RUN_* */
     int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
-    int32_t graph_chunk;        /* steps per captured graph (even), 0 = 64 */
+    int32_t graph_chunk;        /* longest captured step sequence, 1..4096, 0 = 64: lbm_create
+                                   captures, for each starting parity, one graph of graph_chunk
+                                   steps and one of each power of two below it, and lbm_step
+                                   runs any count as replays of these (e.g. 20 = 16 + 4) */
     void* stream;               /* hipStream_t to run on; NULL = library-owned stream */
     void* workspace;            /* nullable device buffer (caller-owned) */
     size_t workspace_bytes;     /* its size; must be >= lbm_workspace_bytes() */
@@ -218,7 +221,8 @@ LBM_API int lbm_workspace_bytes(const lbm_domain_desc* domains, int32_t n_domain
 LBM_API int lbm_create(const lbm_domain_desc* domains, int32_t n_domains,
                const lbm_run_desc* run, lbm_ctx** out);
 
-/* Advance every domain by n_steps >= 0 time steps (async, stream ordered). */
+/* Advance every domain by n_steps >= 0 time steps (async, stream ordered),
+ * as replays of the graphs captured at creation (unless LBM_RUN_NO_GRAPH). */
 LBM_API int lbm_step(lbm_ctx* ctx, int64_t n_steps);
 
 /* Wait for all queued work. */

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -60,7 +61,7 @@ struct DomainHost {
     long long plane = 0;
     size_t n = 0;
     size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0, off_dsbuf = 0;
-    size_t off_ens = 0, off_phibuf = 0, off_bstate = 0, off_bhist = 0;
+    size_t off_ens = 0, off_phibuf = 0, off_bstate = 0, off_bhist = 0, off_cand = 0;
     bool dsbuf = false, phibuf = false;
     double shift = 0;
     int tile_first = 0, tile_count = 0;
@@ -94,7 +95,13 @@ struct lbm_ctx {
     bool budget = false;        // the budget threshold in some domain
     bool elbm = false;          // ELBM collisions (all domains)
     long long steps_done = 0, finalized_for = -1;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // captured step sequences, for each starting parity: graph_chunk steps
+    // and every power of two below it, longest first
+    struct StepGraph {
+        int64_t len;
+        hipGraphExec_t exec;
+    };
+    std::vector<StepGraph> graphs[2];
     std::string err;
     std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
     std::vector<Tile> rows_host;
@@ -136,7 +143,8 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
         return fail(nullptr, LBM_EINVAL, "tile_x must be 0 or 256 (columns of one tile)");
     if (run->tile_y != 0 && run->tile_y != 1) return fail(nullptr, LBM_EINVAL, "tile_y must be 0 or 1");
     if (run->tile_h < 0 || run->tile_h > kMaxTileH) return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 64]");
-    if (run->graph_chunk < 0 || (run->graph_chunk % 2) != 0) return fail(nullptr, LBM_EINVAL, "graph_chunk must be even");
+    if (run->graph_chunk < 0 || run->graph_chunk > 4096)
+        return fail(nullptr, LBM_EINVAL, "graph_chunk out of range [0, 4096]");
     if (run->probe_capacity < 0) return fail(nullptr, LBM_EINVAL, "probe_capacity < 0");
     const lbm_domain_desc& d0 = doms[0];
     for (int k = 0; k < nd; ++k) {
@@ -272,6 +280,8 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         }
         h.off_ens = off;
         off = align_up(off + kNEns * sizeof(double), kAlign);
+        h.off_cand = off;
+        off = align_up(off + 2 * sizeof(int), kAlign);
         if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {
             h.off_bstate = off;
             off = align_up(off + sizeof(BudgetState), kAlign);
@@ -381,6 +391,7 @@ int upload_domains(lbm_ctx* ctx)
         d.dsbuf = h.dsbuf ? ctx->ws + h.off_dsbuf : nullptr;
         d.phibuf = h.phibuf ? ctx->ws + h.off_phibuf : nullptr;
         d.ens = reinterpret_cast<double*>(ctx->ws + h.off_ens);
+        d.cand = reinterpret_cast<int*>(ctx->ws + h.off_cand);
         d.ens_c = h.d.ens_c;
         d.ens_k = h.d.ens_k;
         d.delta_ens = h.d.delta_ens;
@@ -473,11 +484,11 @@ int reset_counters(lbm_ctx* ctx)
 
 void drop_graphs(lbm_ctx* ctx)
 {
-    for (auto& g : ctx->graph)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto& gs : ctx->graphs) {
+        for (auto& g : gs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        gs.clear();
+    }
 }
 
 // The step kernels work on row segments of kThreads columns; D2Q9 tiles only
@@ -487,21 +498,41 @@ int autotune(lbm_ctx* ctx, int fixed_th)
     return set_tiles(ctx, fixed_th ? fixed_th : kMaxTileH);
 }
 
-int capture(lbm_ctx* ctx, int parity)
+// Capture `len` steps starting at `parity` into one executable graph.
+int capture(lbm_ctx* ctx, int parity, int64_t len)
 {
     hipGraph_t g = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     int rc = LBM_OK;
-    for (int k = 0; k < ctx->graph_chunk && rc == LBM_OK; ++k) rc = launch_one(ctx, (parity + k) % 2);
+    for (int64_t k = 0; k < len && rc == LBM_OK; ++k) rc = launch_one(ctx, int((parity + k) % 2));
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&ctx->graph[parity], g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    ctx->graphs[parity].push_back({len, x});
+    return LBM_OK;
+}
+
+// Every step of lbm_step runs inside a graph: for each starting parity, one
+// graph of graph_chunk steps and one of each power of two below it, so that
+// any count is a few replays (e.g. 20 = 16 + 4).  Captured once, at creation,
+// so that no capture happens inside a caller's timed loop.
+int capture_all(lbm_ctx* ctx)
+{
+    std::vector<int64_t> lens{ctx->graph_chunk};
+    for (int64_t l = 1; l < ctx->graph_chunk; l *= 2) lens.push_back(l);
+    std::sort(lens.begin(), lens.end(), std::greater<int64_t>());
+    for (int parity = 0; parity < 2; ++parity)
+        for (int64_t l : lens) {
+            int rc = capture(ctx, parity, l);
+            if (rc) return rc;
+        }
     return LBM_OK;
 }
 
@@ -674,6 +705,12 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         ctx->own_ws = true;
     }
 
+    // median candidate flags start clear (the collision kernels keep them)
+    for (const auto& h : ctx->dom) {
+        e = hipMemsetAsync(ctx->ws + h.off_cand, 0, 2 * sizeof(int), ctx->stream);
+        if (e != hipSuccess)
+            return bail(fail(nullptr, LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));
+    }
     // budget histograms start zero; every selection level leaves them zero
     for (const auto& h : ctx->dom)
         if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {
@@ -729,6 +766,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         if (!rc && hipMemsetAsync(ctx->ws + h.off_stats, 0, (kNStat + 1) * sizeof(double), ctx->stream) != hipSuccess)
             rc = fail(ctx, LBM_EDEVICE, "hipMemsetAsync stats");
     if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(ctx, LBM_EDEVICE, "sync after create");
+    if (!rc && !(ctx->flags & LBM_RUN_NO_GRAPH)) rc = capture_all(ctx);
     if (rc) {
         g_err = ctx->err;
         return bail(rc);
@@ -741,17 +779,21 @@ int lbm_step(lbm_ctx* ctx, int64_t n_steps)
 {
     if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
     if (n_steps < 0) return fail(ctx, LBM_EINVAL, "n_steps < 0");
-    const bool use_graph = !(ctx->flags & LBM_RUN_NO_GRAPH);
     int64_t since_check = 0;
     while (n_steps > 0) {
         int rc;
-        int64_t done;
+        int64_t done = 0;
         const int parity = int(ctx->steps_done % 2);
-        if (use_graph && n_steps >= ctx->graph_chunk) {
-            if (!ctx->graph[parity] && (rc = capture(ctx, parity))) return rc;
-            HIP_TRY(ctx, hipGraphLaunch(ctx->graph[parity], ctx->stream));
-            done = ctx->graph_chunk;
-        } else {
+        // the longest captured sequence that fits before the next stats point
+        int64_t limit = n_steps;
+        if (ctx->stats_every > 0) limit = std::min<int64_t>(limit, ctx->stats_every - since_check);
+        for (const auto& g : ctx->graphs[parity])
+            if (g.len <= limit) {
+                HIP_TRY(ctx, hipGraphLaunch(g.exec, ctx->stream));
+                done = g.len;
+                break;
+            }
+        if (done == 0) {
             if ((rc = launch_one(ctx, parity))) return rc;
             done = 1;
         }

@@ -99,6 +99,9 @@ struct DomainDev {
     BudgetBucket* bhist;          // [kBudgetBuckets], left zero between levels
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
     void* dsbuf;            // [ny*nx] Delta S' of the last collision (arithmetic type), median only
+    int* cand;              // [2] by step parity: the D2Q9 collision kernel of a step sets its
+                            // slot when a fluid node is a median candidate (Delta S' > delta)
+                            // and clears the other slot for the next step
 };
 
 constexpr int kXcds = 8;   // MI355X: 8 accelerator dies, each with its own L2

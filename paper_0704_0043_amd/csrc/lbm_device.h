@@ -731,9 +731,11 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
 // Partial of a workgroup whose threads hold at most one node each: the
 // sums (FP32 for reduced storage, FP64 for FP64 storage) by a fixed xor
 // butterfly in each wave, the 0/1 counts by ballots, the waves combined in
-// FP64 in order.
+// FP64 in order.  When some wave holds a median candidate, 1 is stored to
+// *cand (nullable).
 template <class S>
-__device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */)
+__device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */,
+                                    int* cand = nullptr)
 {
     S v[8] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent};
 #pragma unroll
@@ -764,6 +766,7 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
         double s = lds[tid];
         for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
         out[tid] = s;
+        if (tid == kSAbove && cand && s != 0.0) *cand = 1;
     }
 }
 

@@ -216,6 +216,9 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     const long long step = a.counter[a.parity];
     // the index of the next step, read by the next launch (which reads buffer 1 - parity)
     if (ridx == 0 && threadIdx.x == 0) a.counter[1 - a.parity] = step + 1;
+    // the next step's candidate flag starts clear (this step's second pass
+    // reads only the slot of this parity)
+    if (ridx == D.row_first && threadIdx.x == 0) D.cand[1 - a.parity] = 0;
     // The ensemble limiters and the GATE reading of the median use every
     // Delta S'.  The FLOOR median only needs the values above delta: its
     // threshold max(median, delta) and its decision are unchanged when every
@@ -320,7 +323,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
             }
         }
     }
-    node_partial(acc, a.rowpart + (long long)ridx * kNStat, red);
+    node_partial(acc, a.rowpart + (long long)ridx * kNStat, red, keep_ds ? D.cand + a.parity : nullptr);
 }
 
 // Second pass: median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the
@@ -469,6 +472,14 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
     const int tidx = tile_of_block(a, 0);
     const Tile t = a.tiles[tidx];
     const DomainDev& D = a.dom[t.domain];
+    if constexpr (!ENS) {
+        // no node of the domain is a median candidate (the collision kernel
+        // raised no flag): nothing to filter, an empty partial
+        if (!(D.limiter & kLimMedian) || D.cand[a.parity] == 0) {
+            if (threadIdx.x < kNStat) partial_slot(a, 1, tidx)[threadIdx.x] = 0.0;
+            return;
+        }
+    }
     AccT<A> acc;
     const int nx = D.nx, ny = D.ny;
     const int x = t.x0 + int(threadIdx.x);
