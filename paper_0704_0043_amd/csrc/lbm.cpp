@@ -25,7 +25,6 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t kAlign = 256;
-constexpr int k1DWidth = kThreads - 2;    // output sites of one D1Q3 workgroup
 
 // D2Q9 tiles: kThreads consecutive columns
 int strips_of(int nx) { return (nx + kThreads - 1) / kThreads; }
@@ -61,7 +60,7 @@ struct DomainHost {
     long long plane = 0;
     size_t n = 0;
     size_t off_buf[2] = {0, 0}, off_mask = 0, off_ds = 0, off_probe = 0, off_stats = 0, off_dsbuf = 0;
-    size_t off_ens = 0, off_phibuf = 0, off_bstate = 0, off_bhist = 0, off_cand = 0;
+    size_t off_ens = 0, off_phibuf = 0, off_bstate = 0, off_bhist = 0;
     bool dsbuf = false, phibuf = false;
     double shift = 0;
     int tile_first = 0, tile_count = 0;
@@ -230,6 +229,36 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
     return LBM_OK;
 }
 
+// Per-domain arrays besides the populations, the record planes and the
+// probe ring, placed from `off`: stats, the Delta S' plane (median filter or
+// a limiter that needs the whole domain), the applied factor (D1Q3 ensemble
+// pass), the ensemble values, the selection state.
+size_t plan_extras(DomainHost& h, int storage, size_t off)
+{
+    h.off_stats = off;
+    off = align_up(off + (kNStat + 1) * sizeof(double), kAlign);
+    const bool ens = deferred(h.d);
+    h.dsbuf = (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN)) || ens;
+    if (h.dsbuf) {
+        h.off_dsbuf = off;
+        off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
+    }
+    h.phibuf = ens && h.d.lattice == LBM_D1Q3;
+    if (h.phibuf) {
+        h.off_phibuf = off;
+        off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
+    }
+    h.off_ens = off;
+    off = align_up(off + kNEns * sizeof(double), kAlign);
+    if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {
+        h.off_bstate = off;
+        off = align_up(off + sizeof(BudgetState), kAlign);
+        h.off_bhist = off;
+        off = align_up(off + kBudgetBuckets * sizeof(BudgetBucket), kAlign);
+    }
+    return off;
+}
+
 // Device layout for the given descriptors.  The tile arrays are sized for the
 // smallest tile shape so any autotuned shape fits.
 void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run, Layout& L)
@@ -265,32 +294,9 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
             h.off_probe = off;
             off = align_up(off + size_t(cap) * 2 * sizeof(float), kAlign);
         }
-        h.off_stats = off;
-        off = align_up(off + (kNStat + 1) * sizeof(double), kAlign);
-        const bool ens = deferred(h.d);
-        h.dsbuf = (h.d.lattice == LBM_D2Q9 && (h.d.limiter & LBM_LIM_MEDIAN)) || ens;
-        if (h.dsbuf) {
-            h.off_dsbuf = off;
-            off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
-        }
-        h.phibuf = ens && h.d.lattice == LBM_D1Q3;
-        if (h.phibuf) {
-            h.off_phibuf = off;
-            off = align_up(off + h.n * (storage == LBM_F64 ? 8 : 4), kAlign);
-        }
-        h.off_ens = off;
-        off = align_up(off + kNEns * sizeof(double), kAlign);
-        h.off_cand = off;
-        off = align_up(off + 2 * sizeof(int), kAlign);
-        if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {
-            h.off_bstate = off;
-            off = align_up(off + sizeof(BudgetState), kAlign);
-            h.off_bhist = off;
-            off = align_up(off + kBudgetBuckets * sizeof(BudgetBucket), kAlign);
-        }
+        off = plan_extras(h, storage, off);
         const int min_h = run->tile_h > 0 ? run->tile_h : kMaxTileH;
-        const int tiles = h.d.lattice == LBM_D2Q9 ? strips_of(h.d.nx) * ((h.d.ny + min_h - 1) / min_h)
-                                                  : (h.d.nx + k1DWidth - 1) / k1DWidth;
+        const int tiles = tiles_of(h.d.lattice, h.d.nx, h.d.ny, min_h);
         L.max_tiles += tiles;
         if (h.d.lattice == LBM_D2Q9) L.nrows += strips_of(h.d.nx) * h.d.ny;
         L.max_n = std::max(L.max_n, h.n);
@@ -324,17 +330,11 @@ std::vector<Tile> build_tiles(lbm_ctx* ctx, int th)
         DomainHost& h = ctx->dom[k];
         h.tile_first = int(spatial.size());
         const int nx = h.d.nx, ny = h.d.ny;
-        if (ctx->lattice == LBM_D2Q9) {
-            const int chunks = (ny + th - 1) / th;
-            for (int r = 0; r < chunks; ++r)
-                for (int x0 = 0; x0 < nx; x0 += kThreads)
-                    spatial.push_back(Tile{int(k), x0, std::min(x0 + kThreads, nx), r * th, std::min(r * th + th, ny),
-                                           r, chunks, (ny - r + chunks - 1) / chunks});
-        } else {
-            for (int x0 = 0; x0 < nx; x0 += k1DWidth)
-                spatial.push_back(Tile{int(k), x0, std::min(x0 + k1DWidth, nx), 0, 1, 0, 1, 1});
-        }
-        h.tile_count = int(spatial.size()) - h.tile_first;
+        const int count = tiles_of(ctx->lattice, nx, ny, th);
+        for (int i = 0; i < count; ++i)
+            spatial.push_back(ctx->lattice == LBM_D2Q9 ? tile_entry2d(int(k), nx, ny, th, i)
+                                                       : tile_entry1d(int(k), nx, i));
+        h.tile_count = count;
     }
     return spatial;
 }
@@ -348,11 +348,56 @@ void build_rows(lbm_ctx* ctx)
     for (size_t k = 0; k < ctx->dom.size(); ++k) {
         DomainHost& h = ctx->dom[k];
         h.row_first = int(ctx->rows_host.size());
-        for (int y = 0; y < h.d.ny; ++y)
-            for (int x0 = 0; x0 < h.d.nx; x0 += kThreads)
-                ctx->rows_host.push_back(Tile{int(k), x0, std::min(x0 + kThreads, h.d.nx), y, y + 1, y, 1, 1});
-        h.row_count = int(ctx->rows_host.size()) - h.row_first;
+        h.row_count = strips_of(h.d.nx) * h.d.ny;
+        for (int i = 0; i < h.row_count; ++i) ctx->rows_host.push_back(row_entry2d(int(k), h.d.nx, i));
     }
+}
+
+// Device view of one domain: device pointers into `base` at the host
+// layout's offsets; the population buffers are b0 and b1.
+DomainDev make_dev(const DomainHost& h, char* base, void* b0, void* b1, int probe_cap, unsigned flags)
+{
+    DomainDev d{};
+    d.buf[0] = b0;
+    d.buf[1] = b1;
+    d.plane = h.plane;
+    d.nx = h.d.nx;
+    d.ny = h.d.ny;
+    d.c = 2.0 * h.d.beta - 1.0;
+    d.shift = h.shift;
+    d.delta_trim = h.d.delta_trim;
+    d.delta_median = h.d.delta_median;
+    d.rho0 = h.d.rho0;
+    d.lid_ux = h.d.lid_ux;
+    d.trim_mode = h.d.trim_mode;
+    d.median_mode = h.d.median_mode;
+    d.probe_x = h.d.probe_x >= 0 ? h.d.probe_x : -1;
+    d.probe_y = h.d.probe_x >= 0 ? h.d.probe_y : -1;
+    d.probe_cap = probe_cap;
+    d.probe = h.d.probe_x >= 0 ? reinterpret_cast<float*>(base + h.off_probe) : nullptr;
+    d.mask = (flags & LBM_RUN_RECORD) ? reinterpret_cast<unsigned char*>(base + h.off_mask) : nullptr;
+    d.dS = (flags & LBM_RUN_RECORD) ? reinterpret_cast<double*>(base + h.off_ds) : nullptr;
+    d.tile_first = h.tile_first;
+    d.tile_count = h.tile_count;
+    d.strips = strips_of(h.d.nx);
+    d.row_first = h.row_first;
+    d.row_count = h.row_count;
+    d.stats = reinterpret_cast<double*>(base + h.off_stats);
+    d.dsbuf = h.dsbuf ? base + h.off_dsbuf : nullptr;
+    d.phibuf = h.phibuf ? base + h.off_phibuf : nullptr;
+    d.ens = reinterpret_cast<double*>(base + h.off_ens);
+    d.ens_c = h.d.ens_c;
+    d.ens_k = h.d.ens_k;
+    d.delta_ens = h.d.delta_ens;
+    d.diffusive = h.d.bc == LBM_BC_CAVITY_DIFFUSIVE ? 1 : 0;
+    d.collision = h.d.collision;
+    d.homothety = h.d.homothety;
+    d.top_k = h.d.top_k;
+    d.limiter = device_limiter(h.d);
+    const bool budget = (h.d.limiter & kLimEnsBudget) || is_topk(h.d);
+    d.bstate = budget ? reinterpret_cast<BudgetState*>(base + h.off_bstate) : nullptr;
+    d.bhist = budget ? reinterpret_cast<BudgetBucket*>(base + h.off_bhist) : nullptr;
+    return d;
 }
 
 int upload_domains(lbm_ctx* ctx)
@@ -361,48 +406,7 @@ int upload_domains(lbm_ctx* ctx)
     dd.assign(ctx->dom.size(), DomainDev{});
     for (size_t k = 0; k < ctx->dom.size(); ++k) {
         const DomainHost& h = ctx->dom[k];
-        DomainDev& d = dd[k];
-        d.buf[0] = ctx->ws + h.off_buf[0];
-        d.buf[1] = ctx->ws + h.off_buf[1];
-        d.plane = h.plane;
-        d.nx = h.d.nx;
-        d.ny = h.d.ny;
-        d.c = 2.0 * h.d.beta - 1.0;
-        d.shift = h.shift;
-        d.delta_trim = h.d.delta_trim;
-        d.delta_median = h.d.delta_median;
-        d.rho0 = h.d.rho0;
-        d.lid_ux = h.d.lid_ux;
-        d.limiter = h.d.limiter;
-        d.trim_mode = h.d.trim_mode;
-        d.median_mode = h.d.median_mode;
-        d.probe_x = h.d.probe_x >= 0 ? h.d.probe_x : -1;
-        d.probe_y = h.d.probe_x >= 0 ? h.d.probe_y : -1;
-        d.probe_cap = ctx->probe_cap;
-        d.probe = h.d.probe_x >= 0 ? reinterpret_cast<float*>(ctx->ws + h.off_probe) : nullptr;
-        d.mask = (ctx->flags & LBM_RUN_RECORD) ? reinterpret_cast<unsigned char*>(ctx->ws + h.off_mask) : nullptr;
-        d.dS = (ctx->flags & LBM_RUN_RECORD) ? reinterpret_cast<double*>(ctx->ws + h.off_ds) : nullptr;
-        d.tile_first = h.tile_first;
-        d.tile_count = h.tile_count;
-        d.strips = strips_of(h.d.nx);
-        d.row_first = h.row_first;
-        d.row_count = h.row_count;
-        d.stats = reinterpret_cast<double*>(ctx->ws + h.off_stats);
-        d.dsbuf = h.dsbuf ? ctx->ws + h.off_dsbuf : nullptr;
-        d.phibuf = h.phibuf ? ctx->ws + h.off_phibuf : nullptr;
-        d.ens = reinterpret_cast<double*>(ctx->ws + h.off_ens);
-        d.cand = reinterpret_cast<int*>(ctx->ws + h.off_cand);
-        d.ens_c = h.d.ens_c;
-        d.ens_k = h.d.ens_k;
-        d.delta_ens = h.d.delta_ens;
-        d.diffusive = h.d.bc == LBM_BC_CAVITY_DIFFUSIVE ? 1 : 0;
-        d.collision = h.d.collision;
-        d.homothety = h.d.homothety;
-        d.top_k = h.d.top_k;
-        d.limiter = device_limiter(h.d);
-        const bool budget = (h.d.limiter & kLimEnsBudget) || is_topk(h.d);
-        d.bstate = budget ? reinterpret_cast<BudgetState*>(ctx->ws + h.off_bstate) : nullptr;
-        d.bhist = budget ? reinterpret_cast<BudgetBucket*>(ctx->ws + h.off_bhist) : nullptr;
+        dd[k] = make_dev(h, ctx->ws, ctx->ws + h.off_buf[0], ctx->ws + h.off_buf[1], ctx->probe_cap, ctx->flags);
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_dom(), dd.data(), dd.size() * sizeof(DomainDev), hipMemcpyHostToDevice,
                                 ctx->stream));
@@ -443,30 +447,47 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     return a;
 }
 
-// One step of every domain.  With `ev` (three events) the launches are
-// bracketed for per-kernel timing: ev[0] | collision | ev[1] | median | ev[2].
+// The kernels one step launches (what a context or a static call runs).
+struct StepKind {
+    int storage, lattice, qe, ds, bc;
+    bool elbm, median_pass, ens_pass, budget;
+};
+
+// One step of every domain of `a`.  With `ev` (three events) the launches
+// are bracketed for per-kernel timing: ev[0] | collision | ev[1] | rest | ev[2].
+hipError_t launch_step(const StepKind& k, const StepArgs& a, hipStream_t s, hipEvent_t* ev = nullptr)
+{
+    hipError_t e = hipSuccess;
+    if (ev) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) {
+        if (k.lattice == LBM_D2Q9)
+            e = launch_step2d(k.storage, k.qe, k.ds, k.bc, a, k.elbm ? 2 : 0, s);
+        else
+            e = launch_step1d(k.storage, k.qe, k.ds, k.bc, a, k.elbm ? 2 : 0, s);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+    // ensemble limiters: E(Delta S') of this step first (Sec. 3.3, 3.4)
+    if (e == hipSuccess && k.ens_pass) e = launch_ens_prepare(a, s);
+    if (e == hipSuccess && k.budget) e = launch_budget(k.storage, k.bc, a, s);
+    if (e == hipSuccess && (k.median_pass || k.ens_pass)) {
+        if (k.lattice == LBM_D2Q9)
+            e = launch_step2d(k.storage, k.qe, k.ds, k.bc, a, 1, s);
+        else
+            e = launch_step1d(k.storage, k.qe, k.ds, k.bc, a, 1, s);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
+    return e;
+}
+
+StepKind step_kind(const lbm_ctx* ctx)
+{
+    return StepKind{ctx->storage, ctx->lattice, ctx->qe, ctx->ds, ctx->bc, ctx->elbm, ctx->median_pass,
+                    ctx->ens_pass, ctx->budget};
+}
+
 int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
 {
-    const StepArgs a = step_args(ctx, parity);
-    hipError_t e = hipSuccess;
-    if (ev) e = hipEventRecord(ev[0], ctx->stream);
-    if (e == hipSuccess) {
-        if (ctx->lattice == LBM_D2Q9)
-            e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->elbm ? 2 : 0, ctx->stream);
-        else
-            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, ctx->elbm ? 2 : 0, ctx->stream);
-    }
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
-    // ensemble limiters: E(Delta S') of this step first (Sec. 3.3, 3.4)
-    if (e == hipSuccess && ctx->ens_pass) e = launch_ens_prepare(a, ctx->stream);
-    if (e == hipSuccess && ctx->budget) e = launch_budget(ctx->storage, ctx->bc, a, ctx->stream);
-    if (e == hipSuccess && (ctx->median_pass || ctx->ens_pass)) {
-        if (ctx->lattice == LBM_D2Q9)
-            e = launch_step2d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
-        else
-            e = launch_step1d(ctx->storage, ctx->qe, ctx->ds, ctx->bc, a, 1, ctx->stream);
-    }
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], ctx->stream);
+    const hipError_t e = launch_step(step_kind(ctx), step_args(ctx, parity), ctx->stream, ev);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return LBM_OK;
 }
@@ -705,12 +726,6 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         ctx->own_ws = true;
     }
 
-    // median candidate flags start clear (the collision kernels keep them)
-    for (const auto& h : ctx->dom) {
-        e = hipMemsetAsync(ctx->ws + h.off_cand, 0, 2 * sizeof(int), ctx->stream);
-        if (e != hipSuccess)
-            return bail(fail(nullptr, LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e)));
-    }
     // budget histograms start zero; every selection level leaves them zero
     for (const auto& h : ctx->dom)
         if ((h.d.limiter & kLimEnsBudget) || is_topk(h.d)) {

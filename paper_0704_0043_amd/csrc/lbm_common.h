@@ -99,9 +99,6 @@ struct DomainDev {
     BudgetBucket* bhist;          // [kBudgetBuckets], left zero between levels
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
     void* dsbuf;            // [ny*nx] Delta S' of the last collision (arithmetic type), median only
-    int* cand;              // [2] by step parity: the D2Q9 collision kernel of a step sets its
-                            // slot when a fluid node is a median candidate (Delta S' > delta)
-                            // and clears the other slot for the next step
 };
 
 constexpr int kXcds = 8;   // MI355X: 8 accelerator dies, each with its own L2
@@ -126,6 +123,36 @@ __host__ __device__ inline int xcd_spatial(int b, int T)
 struct Tile {
     int domain, x0, x1, y0, y1, ys, ystep, yn;
 };
+
+constexpr int k1DWidth = kThreads - 2;   // output sites of one D1Q3 workgroup
+
+// Entry i of a domain's work tables (host and device build them alike):
+// D2Q9 tiles of kThreads columns by th rows in spatial order (row chunk, then
+// column strip); D2Q9 row segments of kThreads columns in row-major order;
+// D1Q3 tiles of k1DWidth sites.
+__host__ __device__ inline Tile tile_entry2d(int domain, int nx, int ny, int th, int i)
+{
+    const int strips = (nx + kThreads - 1) / kThreads;
+    const int chunks = (ny + th - 1) / th;
+    const int r = i / strips, x0 = (i - r * strips) * kThreads;
+    return Tile{domain, x0, x0 + kThreads < nx ? x0 + kThreads : nx, r * th, r * th + th < ny ? r * th + th : ny,
+                r, chunks, (ny - r + chunks - 1) / chunks};
+}
+__host__ __device__ inline Tile row_entry2d(int domain, int nx, int i)
+{
+    const int strips = (nx + kThreads - 1) / kThreads;
+    const int y = i / strips, x0 = (i - y * strips) * kThreads;
+    return Tile{domain, x0, x0 + kThreads < nx ? x0 + kThreads : nx, y, y + 1, y, 1, 1};
+}
+__host__ __device__ inline Tile tile_entry1d(int domain, int nx, int i)
+{
+    const int x0 = i * k1DWidth;
+    return Tile{domain, x0, x0 + k1DWidth < nx ? x0 + k1DWidth : nx, 0, 1, 0, 1, 1};
+}
+__host__ __device__ inline int tiles_of(int lattice, int nx, int ny, int th)
+{
+    return lattice == kD2Q9 ? ((nx + kThreads - 1) / kThreads) * ((ny + th - 1) / th) : (nx + k1DWidth - 1) / k1DWidth;
+}
 
 struct StepArgs {
     const DomainDev* dom;

@@ -295,6 +295,105 @@ struct SiteScalars {
     bool nonpos;
 };
 
+// ---- FP32 equilibrium without a coherent drift ------------------------------
+// In FP32 the moments are sums of O(0.1) shifts whose result is much smaller
+// (the shift removes only the rest state), and the lattice weights 4/9, 1/9,
+// 1/36 (2/3, 1/6 in 1-D) round to one mantissa with the same relative error
+// e = 7.45e-9: the equilibrium's momentum then comes out as (1 + 2e) j, and
+// the sums' rounding lands alike at neighbouring nodes.  Both errors repeat
+// at every step of a slowly varying flow and add up (1e-5 of the velocity
+// after 1e3 steps of a lid-driven cavity), where an unbiased rounding of the
+// stored state alone stays near 1e-7.  So the FP32 path sums mass and
+// momentum with error-free transformations (TwoSum, Knuth) and takes the
+// momentum term with coefficients whose identity sum_i a_i v_i v_i = 1 holds
+// exactly in binary: a = fl(1/3) on the axes and (1 - 2 fl(1/3)) / 4
+// (exactly representable) on the diagonals of D2Q9, 1/2 in D1Q3.  The
+// entropic f* (square roots and reciprocals) is brought back to the node's
+// mass and momentum afterwards along the same coefficients.
+
+// s + e = a + b exactly (round to nearest)
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// sum_i c_i g_i with c_i in {-1, 0, 1}, compensated (rounded once at the end)
+template <int Q, class C>
+__device__ __forceinline__ float comp_sum(const float (&g)[Q], C coef)
+{
+    float s = 0.0f, c = 0.0f;
+    bool first = true;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int k = coef(i);
+        if (k == 0) continue;
+        const float x = k > 0 ? g[i] : -g[i];
+        if (first) {
+            s = x;
+            first = false;
+        } else {
+            float e;
+            two_sum(s, x, s, e);
+            c += e;
+        }
+    }
+    return s + c;
+}
+
+// mass sum_i g_i and momentum sum_i v_i g_i, compensated.  D2Q9: sums and
+// differences of opposite populations first (the diagonal difference
+// g5 - g7 serves both components), then the short sums, each rounding error
+// kept and added back once.
+template <int LAT>
+__device__ __forceinline__ void comp_moments(const float (&g)[Lat<LAT>::Q], float& dr, float& jx, float& jy)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    if constexpr (LAT == kD2Q9) {
+        float p13, f13, p24, f24, p57, f57, p68, f68, s, e1, e2, e3, e4;
+        two_sum(g[1], g[3], p13, f13);
+        two_sum(g[2], g[4], p24, f24);
+        two_sum(g[5], g[7], p57, f57);
+        two_sum(g[6], g[8], p68, f68);
+        two_sum(p13, p24, s, e1);
+        two_sum(s, p57, s, e2);
+        two_sum(s, p68, s, e3);
+        two_sum(s, g[0], s, e4);
+        dr = s + (((f13 + f24) + (f57 + f68)) + ((e1 + e2) + (e3 + e4)));
+        float d13, e13, d57, e57, d86, e86, d24, e24, sx, ex1, ex2, sy, ey1, ey2;
+        two_sum(g[1], -g[3], d13, e13);
+        two_sum(g[5], -g[7], d57, e57);
+        two_sum(g[8], -g[6], d86, e86);
+        two_sum(g[2], -g[4], d24, e24);
+        two_sum(d13, d57, sx, ex1);
+        two_sum(sx, d86, sx, ex2);
+        two_sum(d24, d57, sy, ey1);
+        two_sum(sy, -d86, sy, ey2);
+        jx = sx + (((e13 + e57) + e86) + (ex1 + ex2));
+        jy = sy + (((e24 + e57) - e86) + (ey1 + ey2));
+    } else {
+        dr = comp_sum<Q>(g, [](int) { return 1; });
+        jx = comp_sum<Q>(g, [](int i) { return L::vx(i); });
+        jy = 0.0f;
+    }
+}
+
+// momentum coefficient a_i = 3 w_i of population i, with sum_i a_i v_i v_i = 1
+// exactly in FP32
+template <int LAT>
+__device__ __forceinline__ float mom_coef(int i)
+{
+    if constexpr (LAT == kD2Q9) {
+        constexpr float a1 = 0.333333343267440796f;        // fl(1/3) = 11184811 2^-25
+        constexpr float a5 = 0.0833333283662796021f;       // (1 - 2 a1) / 4 = 5592405 2^-26
+        return i == 0 ? 0.0f : (i <= 4 ? a1 : a5);
+    } else {
+        return i == 0 ? 0.0f : 0.5f;
+    }
+}
+
 // Moments (eq. macro_dis) and the shifted equilibrium g*_i = f*_i - w_i shift
 // of a state g in shift form.  Also used on a limited state: the limiter keeps
 // rho and u, so its f* is the one it was limited toward.
@@ -304,27 +403,43 @@ __device__ __forceinline__ void moments_equilibrium(const A (&g)[Lat<LAT>::Q], A
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q;
-    dr = 0;
-    jx = 0;
-    jy = 0;
+    constexpr bool fp32 = sizeof(A) == 4;
+    if constexpr (fp32) {
+        comp_moments<LAT>(g, dr, jx, jy);
+    } else {
+        dr = 0;
+        jx = 0;
+        jy = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        dr += g[i];
-        if (L::vx(i) > 0) jx += g[i];
-        if (L::vx(i) < 0) jx -= g[i];
-        if (L::vy(i) > 0) jy += g[i];
-        if (L::vy(i) < 0) jy -= g[i];
+        for (int i = 0; i < Q; ++i) {
+            dr += g[i];
+            if (L::vx(i) > 0) jx += g[i];
+            if (L::vx(i) < 0) jx -= g[i];
+            if (L::vy(i) > 0) jy += g[i];
+            if (L::vy(i) < 0) jy -= g[i];
+        }
     }
     rho = shift + dr;
     const A inv = rcp(rho);
     ux = jx * inv;
     uy = jy * inv;
+    if constexpr (QE == kPoly && fp32) {
+        // w_i (dr + rho (9 (v_i.u)^2 / 2 - 3 u^2 / 2)) + a_i v_i.j
+        const A base = A(-1.5) * (ux * ux + uy * uy);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const A cu = A(L::vx(i)) * ux + A(L::vy(i)) * uy;
+            const A cj = A(L::vx(i)) * jx + A(L::vy(i)) * jy;
+            const A even = A(L::w(i)) * (dr + rho * (base + A(4.5) * cu * cu));
+            gs[i] = __builtin_fmaf(mom_coef<LAT>(i), cj, even);
+        }
+        return;
+    }
     A E[Q];
     if constexpr (QE == kPoly) {
         // rho E_i = 3 v_i.j + rho (9 (v_i.u)^2 / 2 - 3 u^2 / 2): the linear
         // term is taken from j itself, so the momentum of f* is j up to the
-        // rounding of sums, whatever the rounding of u = j / rho (a biased
-        // reciprocal would otherwise feed a drift of momentum every step)
+        // rounding of sums, whatever the rounding of u = j / rho
         const A base = A(-1.5) * (ux * ux + uy * uy);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -339,6 +454,17 @@ __device__ __forceinline__ void moments_equilibrium(const A (&g)[Lat<LAT>::Q], A
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) gs[i] = A(L::w(i)) * (dr + E[i]);
+    if constexpr (fp32) {
+        // entropic f* in FP32: bring the equilibrium's mass and momentum
+        // (summed without loss) back to the node's, along w_i and the exact
+        // momentum coefficients
+        float dre, jxe, jye;
+        comp_moments<LAT>(gs, dre, jxe, jye);
+        const float dd = dr - dre, dx = jx - jxe, dy = jy - jye;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            gs[i] += A(L::w(i)) * dd + mom_coef<LAT>(i) * (A(L::vx(i)) * dx + A(L::vy(i)) * dy);
+    }
 }
 
 // h with its limit h(-1) = 1 (a population at exactly zero)
@@ -731,11 +857,9 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
 // Partial of a workgroup whose threads hold at most one node each: the
 // sums (FP32 for reduced storage, FP64 for FP64 storage) by a fixed xor
 // butterfly in each wave, the 0/1 counts by ballots, the waves combined in
-// FP64 in order.  When some wave holds a median candidate, 1 is stored to
-// *cand (nullable).
+// FP64 in order.
 template <class S>
-__device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */,
-                                    int* cand = nullptr)
+__device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */)
 {
     S v[8] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent};
 #pragma unroll
@@ -766,7 +890,6 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
         double s = lds[tid];
         for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
         out[tid] = s;
-        if (tid == kSAbove && cand && s != 0.0) *cand = 1;
     }
 }
 

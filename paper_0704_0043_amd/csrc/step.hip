@@ -216,9 +216,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     const long long step = a.counter[a.parity];
     // the index of the next step, read by the next launch (which reads buffer 1 - parity)
     if (ridx == 0 && threadIdx.x == 0) a.counter[1 - a.parity] = step + 1;
-    // the next step's candidate flag starts clear (this step's second pass
-    // reads only the slot of this parity)
-    if (ridx == D.row_first && threadIdx.x == 0) D.cand[1 - a.parity] = 0;
+
     // The ensemble limiters and the GATE reading of the median use every
     // Delta S'.  The FLOOR median only needs the values above delta: its
     // threshold max(median, delta) and its decision are unchanged when every
@@ -323,7 +321,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
             }
         }
     }
-    node_partial(acc, a.rowpart + (long long)ridx * kNStat, red, keep_ds ? D.cand + a.parity : nullptr);
+    node_partial(acc, a.rowpart + (long long)ridx * kNStat, red);
 }
 
 // Second pass: median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the
@@ -473,9 +471,8 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
     const Tile t = a.tiles[tidx];
     const DomainDev& D = a.dom[t.domain];
     if constexpr (!ENS) {
-        // no node of the domain is a median candidate (the collision kernel
-        // raised no flag): nothing to filter, an empty partial
-        if (!(D.limiter & kLimMedian) || D.cand[a.parity] == 0) {
+        // no median filter in this domain: an empty partial
+        if (!(D.limiter & kLimMedian)) {
             if (threadIdx.x < kNStat) partial_slot(a, 1, tidx)[threadIdx.x] = 0.0;
             return;
         }
@@ -538,7 +535,9 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                 if (D.limiter & kLimTopK) cand = cand || inf || mx > A(D.delta_trim);
             }
         }
-        if ((D.limiter & kLimMedian) && sparse) {
+        active = __syncthreads_or(cand);
+        // staged only for a tile that has something to filter
+        if (active && (D.limiter & kLimMedian) && sparse) {
             const int nr = rows + 2;
             for (int idx = int(threadIdx.x); idx < 3 * nr; idx += kThreads) {
                 const int slot = idx / nr, ry = idx - slot * nr;
@@ -546,8 +545,8 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                 const long long seg = (long long)D.row_first + (long long)row_of(t.y0 - 1 + ry) * D.strips + s3;
                 sflag[slot][ry] = int(a.rowpart[seg * kNStat + kSAbove]);
             }
+            __syncthreads();
         }
-        active = __syncthreads_or(cand);
     }
     if (active && x < t.x1) {
         const long long plane = D.plane;

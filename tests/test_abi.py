@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -125,3 +126,4 @@ def test_mixed_batches_are_rejected(L):
         L.lbm_workspace_bytes([L.Domain(), L.Domain()], L.Run(tile_x=96))
     with pytest.raises(L.LbmError):
         L.lbm_workspace_bytes([L.Domain()], L.Run(tile_h=65))
+

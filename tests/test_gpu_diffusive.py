@@ -82,11 +82,45 @@ def test_batch_of_diffusive_cavities_fp64():
             assert sg["n_filtered"] == st.n_filtered
 
 
-def test_diffusive_cavity_fp32():
-    """FP32 shifted storage, 64 x 64 at Re = 5000, 1000 steps, against the
-    FP64 oracle: gated at the worst-case storage-rounding bound
-    n sum_i u_r max|g_i| (one rounding of every shifted population per step,
-    u_r = 2^-24), the gate of the reduced-precision tests."""
+def test_diffusive_cavity_fp32_short_horizon():
+    """FP32 shifted storage, 64 x 64 at Re = 5000 with the median filter on
+    the exact Delta S, 100 steps, against the FP64 oracle: rho / rho0 and
+    u / u0 within 1e-5, and the filter's decisions of the last step equal
+    except where the oracle's Delta S' lies within 1e-3 (relative) of its
+    threshold max(median, delta) (FP32 Delta S' carries an error of order
+    1e-4 relative, so such decisions may go either way)."""
+    import median_pins as mp
+    L = lbm()
+    o = orc()
+    n, steps = 64, 100
+    rho, u = wl.cavity_rest(n, rho0=1.0)
+    d = L.Domain(lattice=D2Q9, nx=n, ny=n, beta=wl.beta_from_nu(0.1 * n / 5000), qe=1, limiter=2, bc=DIFF,
+                 lid_ux=0.1, delta_median=1e-3, rho_init=rho, u_init=u)
+    with L.lbm_create([d], L.Run(storage=1, flags=L.LBM_RUN_RECORD)) as ctx:
+        L.lbm_step(ctx, steps)
+        rg, ug = L.lbm_moments(ctx)
+        mg, _ = L.lbm_limiter_mask(ctx)
+    p = o.make_params(lattice=2, nx=n, ny=n, beta=d.beta, qe=1, limiter=2, bc=DIFF, lid_ux=0.1, delta_median=1e-3)
+    f = o.init_equilibrium(p, rho, u)
+    _, mo, dso = o.step(p, f, steps, record=True)
+    ro, ux, uy = o.moments(2, f)
+    eu = max(np.abs(ug[0] - ux).max(), np.abs(ug[1] - uy).max()) / 0.1
+    er = np.abs(rg - ro).max()
+    med = mp.median_cavity(np.where((mo & 8) != 0, 0.0, dso))
+    thr = np.maximum(med, 1e-3)
+    close = np.abs(dso - thr) <= 1e-3 * thr
+    diff = (mg & 2) != (mo & 2)
+    say(f"[diffusive fp32 x{steps}] |u - u_ref|/u0 {eu:.2e}  |rho - rho_ref| {er:.2e}  filter decisions "
+        f"differing {int(diff.sum())} (all within the margin: {not (diff & ~close).any()})")
+    assert er <= 1e-5 and eu <= 1e-5
+    assert not (diff & ~close).any()
+
+
+def test_diffusive_cavity_fp32_drift_report():
+    """The same flow over 1000 steps: the FP32 - FP64 difference is reported
+    (filter decisions taken on either side of a threshold compound over the
+    run; this is a report, and the assertion only guards against a run that
+    leaves the FP64 solution altogether)."""
     L = lbm()
     o = orc()
     n = 64
@@ -102,8 +136,5 @@ def test_diffusive_cavity_fp32():
     ro, ux, uy = o.moments(2, f)
     eu = max(np.abs(ug[0] - ux).max(), np.abs(ug[1] - uy).max()) / 0.1
     er = np.abs(rg - ro).max()
-    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
-    bound = 1000 * 2.0 ** -24 * np.abs(f.reshape(9, -1) - w9[:, None]).max(axis=1).sum()
-    say(f"[diffusive fp32] |u - u_ref|/u0 {eu:.2e}  |rho - rho_ref| {er:.2e}  (bound rho {bound:.2e}, "
-        f"u {2 * bound / 0.1:.2e})")
-    assert er <= bound and eu <= 2 * bound / 0.1
+    say(f"[diffusive fp32 x1000 drift] |u - u_ref|/u0 {eu:.2e}  |rho - rho_ref| {er:.2e}")
+    assert eu < 1e-2 and er < 1e-3
