@@ -271,6 +271,55 @@ LBM_API int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms);
 /* Release everything the context owns.  NULL is accepted. */
 LBM_API void lbm_destroy(lbm_ctx* ctx);
 
+/* Bytes of the static device array behind lbm_step_static (per GPU). */
+#define LBM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+/* doubles written to lbm_step_static's stats array */
+#define LBM_STATIC_NSTATS 14
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): advance
+ * one domain by n_steps with the kernels of lbm_step, on population buffers
+ * the caller owns, without any allocation.  Every other array a step uses
+ * (the domain view, the work tables, the reduction partials, the Delta S'
+ * plane, the step counters, the stats) lives in one
+ * static device array of LBM_STATIC_SCRATCH_BYTES, one per GPU, which the
+ * library holds until the process ends.  All calls on one GPU share it:
+ * calls that overlap in time on one GPU (from two host threads, or on two
+ * streams) race and give wrong results; calls in stream order are safe.
+ * Each call clears what must start at zero (counters, stats, the
+ * selection histogram) with its own kernels and launches nothing else, so a
+ * call can be captured into a HIP graph.
+ *   domain   one domain, as for lbm_create; f_init, rho_init and u_init must
+ *            be NULL and probe_x, probe_y -1 (else LBM_EINVAL).
+ *   storage  enum lbm_storage: the element type of f0 and f1.
+ *   stream   hipStream_t to run on (NULL: the null stream); the device is
+ *            the calling thread's current device.
+ *   f0, f1   two distinct device buffers of Q * nx * ny elements of the
+ *            storage type, planes [i][y][x] without padding (plane =
+ *            nx * ny); F64 holds populations, the other types the shift
+ *            g_i = f_i - w_i rho0.  A buffer holds the populations as they
+ *            leave the nodes, before free flight: plane i at node x holds
+ *            f_i(x + v_i) of the state f(x, t) of eq. (lbgkLB) (wrapped on a
+ *            periodic grid; off a non-periodic edge, f_opp(i)(x)), which is
+ *            how lbm_set_populations stores a state.  f0 holds the state at
+ *            entry; step t reads f0 when t is even and f1 when odd and
+ *            writes the other, so after n_steps the state is in f0 for even
+ *            n_steps and in f1 for odd.  Caller-owned.
+ *   n_steps  >= 0 (0 launches nothing).
+ *   stats    nullable device array of LBM_STATIC_NSTATS doubles: the FP64
+ *            sums of the last step in the order mass, mom_x, mom_y,
+ *            sum_dS_pre, sum_dS_post, max_dS, limiter_production,
+ *            n_trimmed, n_filtered, n_nonpositive, n_nonfinite, n_fluid,
+ *            n_ensemble, n_positivity (as in lbm_entropy_stats_t).
+ * Asynchronous (stream ordered).  Errors: LBM_EINVAL (descriptor, buffers,
+ * n_steps < 0); LBM_ENOMEM when the domain needs more scratch than
+ * LBM_STATIC_SCRATCH_BYTES (D2Q9 in FP32 with the median filter needs about
+ * 4.7 bytes per node: up to some 14 million nodes; FP64 about 8.7); these
+ * are detected before anything is launched; LBM_EDEVICE for a HIP error.
+ * The message is in lbm_last_error(NULL). */
+LBM_API int lbm_step_static(const lbm_domain_desc* domain, int32_t storage, void* stream, void* f0, void* f1,
+                            int64_t n_steps, double* stats);
+
 LBM_API const char* lbm_last_error(const lbm_ctx* ctx);
 LBM_API const char* lbm_strerror(int code);
 

@@ -37,6 +37,7 @@ COMMON = [
 def _units():
     units = [(os.path.join(CSRC, "step.hip"), f"step_st{k}.o", [f"-DLBM_ST={k}"]) for k in range(4)]
     units.append((os.path.join(CSRC, "aux.hip"), "aux.o", []))
+    units.append((os.path.join(CSRC, "static_step.hip"), "static_step.o", []))
     units.append((os.path.join(CSRC, "lbm.cpp"), "lbm.o", ["-x", "hip"]))
     return units
 

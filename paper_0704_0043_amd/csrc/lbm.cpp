@@ -622,6 +622,43 @@ int read_stats(lbm_ctx* ctx, int32_t d, lbm_entropy_stats_t* out)
     return s.n_nonfinite > 0 ? fail(ctx, LBM_EUNSTABLE, "non-finite moments in the last step") : LBM_OK;
 }
 
+// Layout of lbm_step_static's arrays in the static scratch array: one
+// domain, tight planes (plane = nx ny), no record planes, no probe.
+struct StaticLayout {
+    size_t off_dom = 0, off_tiles = 0, off_rows = 0, off_partials = 0, off_rowpart = 0, off_counter = 0, total = 0;
+    int ntiles = 0, nrows = 0;
+};
+
+void plan_static(const lbm_domain_desc& d, int storage, DomainHost& h, StaticLayout& L)
+{
+    h.d = d;
+    h.d.rho_init = h.d.u_init = h.d.f_init = nullptr;
+    h.q = q_of(d.lattice);
+    h.n = size_t(d.nx) * d.ny;
+    h.plane = (long long)h.n;
+    h.shift = storage == LBM_F64 ? 0.0 : d.rho0;
+    L.ntiles = tiles_of(d.lattice, d.nx, d.ny, kMaxTileH);
+    L.nrows = d.lattice == LBM_D2Q9 ? strips_of(d.nx) * d.ny : 0;
+    h.tile_first = 0;
+    h.tile_count = L.ntiles;
+    h.row_first = 0;
+    h.row_count = L.nrows;
+    size_t off = 0;
+    L.off_dom = off;
+    off = align_up(off + sizeof(DomainDev), kAlign);
+    L.off_tiles = off;
+    off = align_up(off + size_t(L.ntiles) * sizeof(Tile), kAlign);
+    L.off_rows = off;
+    off = align_up(off + size_t(L.nrows) * sizeof(Tile), kAlign);
+    L.off_partials = off;
+    off = align_up(off + size_t(4) * L.ntiles * kNStat * sizeof(double), kAlign);
+    L.off_rowpart = off;
+    off = align_up(off + size_t(L.nrows) * kNStat * sizeof(double), kAlign);
+    L.off_counter = off;
+    off = align_up(off + 2 * sizeof(long long), kAlign);
+    L.total = plan_extras(h, storage, off);
+}
+
 void release(lbm_ctx* ctx)
 {
     if (!ctx) return;
@@ -979,5 +1016,80 @@ int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
 }
 
 void lbm_destroy(lbm_ctx* ctx) { release(ctx); }
+
+int lbm_step_static(const lbm_domain_desc* domain, int32_t storage, void* stream, void* f0, void* f1,
+                    int64_t n_steps, double* stats)
+{
+    if (!domain) return fail(nullptr, LBM_EINVAL, "domain is NULL");
+    lbm_run_desc run;
+    std::memset(&run, 0, sizeof(run));
+    run.struct_size = sizeof(run);
+    run.storage = storage;
+    int rc = validate(domain, 1, &run);
+    if (rc) return rc;
+    if (!f0 || !f1 || f0 == f1) return fail(nullptr, LBM_EINVAL, "f0 and f1 must be two distinct device buffers");
+    if (n_steps < 0) return fail(nullptr, LBM_EINVAL, "n_steps < 0");
+    if (domain->f_init || domain->rho_init || domain->u_init)
+        return fail(nullptr, LBM_EINVAL, "f_init, rho_init and u_init must be NULL: the state is in f0");
+    if (domain->probe_x >= 0 || domain->probe_y >= 0)
+        return fail(nullptr, LBM_EINVAL, "no probe trace without a context (probe_x, probe_y must be -1)");
+    DomainHost h;
+    StaticLayout L;
+    plan_static(*domain, storage, h, L);
+    if (L.total > kStaticScratchBytes)
+        return fail(nullptr, LBM_ENOMEM,
+                    "lbm_step_static: the domain needs " + std::to_string(L.total) +
+                        " bytes of static scratch, more than the " + std::to_string(kStaticScratchBytes) +
+                        " the library holds per GPU (use lbm_create / lbm_step)");
+    if (n_steps == 0) return LBM_OK;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    char* base = nullptr;
+    if (e == hipSuccess) e = static_scratch(device, &base);
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, std::string("static scratch: ") + hipGetErrorString(e));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const DomainDev dd = make_dev(h, base, f0, f1, 1, 0);
+    DomainDev* dom = reinterpret_cast<DomainDev*>(base + L.off_dom);
+    Tile* tiles = reinterpret_cast<Tile*>(base + L.off_tiles);
+    Tile* rows = reinterpret_cast<Tile*>(base + L.off_rows);
+    long long* counter = reinterpret_cast<long long*>(base + L.off_counter);
+    e = launch_static_setup(dd, domain->lattice, dom, tiles, L.ntiles, rows, L.nrows, kMaxTileH, counter, s);
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, std::string("static setup: ") + hipGetErrorString(e));
+    StepKind k;
+    k.storage = storage;
+    k.lattice = domain->lattice;
+    k.qe = domain->qe;
+    k.ds = domain->ds_form;
+    k.bc = is_cavity(domain->bc) ? kCavity : domain->bc;
+    k.elbm = domain->collision == LBM_COLL_ELBM;
+    k.median_pass = domain->lattice == LBM_D2Q9 && (domain->limiter & LBM_LIM_MEDIAN);
+    k.ens_pass = deferred(*domain);
+    k.budget = (domain->limiter & kLimEnsBudget) || is_topk(*domain);
+    StepArgs a;
+    a.dom = dom;
+    a.tiles = tiles;
+    a.ntiles = L.ntiles;
+    a.ndomains = 1;
+    a.parity = 0;
+    a.flags = 0;
+    a.partials = reinterpret_cast<double*>(base + L.off_partials);
+    a.median_pass = (k.median_pass || k.ens_pass) ? 1 : 0;
+    a.ens_pass = k.ens_pass ? 1 : 0;
+    a.budget = k.budget ? 1 : 0;
+    a.rows = rows;
+    a.nrows = L.nrows;
+    a.rowpart = reinterpret_cast<double*>(base + L.off_rowpart);
+    a.counter = counter;
+    for (int64_t t = 0; t < n_steps && e == hipSuccess; ++t) {
+        a.parity = int(t % 2);
+        e = launch_step(k, a, s);
+    }
+    if (e == hipSuccess && stats) {
+        e = launch_finalize(a, int((n_steps - 1) % 2), n_steps, s);
+        if (e == hipSuccess) e = launch_static_stats(dom, h.shift * double(h.n), stats, s);
+    }
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, std::string("lbm_step_static: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbm.h"
+
 namespace lbm {
 
 enum { kD1Q3 = 1, kD2Q9 = 2 };
@@ -171,6 +173,15 @@ struct StepArgs {
     double* rowpart;        // [nrows][kNStat]: collision partials of the last step
     long long* counter;     // [2] step index by parity
 };
+
+// Allocation-free stepping (lbm_step_static): bytes of the per-GPU static
+// device array that holds everything but the caller's population buffers.
+constexpr size_t kStaticScratchBytes = LBM_STATIC_SCRATCH_BYTES;
+// its address on `device` (looked up once per device; `device` must be current)
+hipError_t static_scratch(int device, char** ptr);
+hipError_t launch_static_setup(const DomainDev& dd, int lattice, DomainDev* dom, Tile* tiles, int ntiles, Tile* rows,
+                               int nrows, int th, long long* counter, hipStream_t s);
+hipError_t launch_static_stats(const DomainDev* dom, double shift_mass, double* out, hipStream_t s);
 
 // Launchers (one per storage type / lattice), defined in the .hip files.
 // kernel 0: collision kernel (LBGK); kernel 2: the same with the ELBM collision;

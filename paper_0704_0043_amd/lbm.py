@@ -118,6 +118,8 @@ SIGNATURES = {
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lbm_beta_from_nu": (ctypes.c_double, [ctypes.c_double]),
     "lbm_abi_version": (ctypes.c_int, []),
+    "lbm_step_static": (ctypes.c_int, [ctypes.POINTER(lbm_domain_desc), ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, _dp]),
 }
 
 
@@ -363,6 +365,24 @@ def lbm_kernel_times(ctx: Context, n_steps: int):
 
 def lbm_destroy(ctx: Context) -> None:
     ctx.close()
+
+
+LBM_STATIC_SCRATCH_BYTES = 64 << 20
+LBM_STATIC_NSTATS = 14
+STATIC_STATS_FIELDS = ("mass", "mom_x", "mom_y", "sum_dS_pre", "sum_dS_post", "max_dS", "limiter_production",
+                       "n_trimmed", "n_filtered", "n_nonpositive", "n_nonfinite", "n_fluid", "n_ensemble",
+                       "n_positivity")
+
+
+def lbm_step_static(domain: Domain, storage: int, f0: int, f1: int, n_steps: int, stream: int | None = None,
+                    stats: int | None = None) -> None:
+    """Allocation-free stepping on caller-owned device buffers (device
+    pointers as ints): the state starts in f0 and ends in f0 (even n_steps)
+    or f1 (odd); `stats` is a device pointer to LBM_STATIC_NSTATS doubles."""
+    d = domain.to_c()
+    _check(lib().lbm_step_static(ctypes.byref(d), int(storage), stream or None, ctypes.c_void_p(f0),
+                                 ctypes.c_void_p(f1), int(n_steps),
+                                 ctypes.cast(ctypes.c_void_p(stats), _dp) if stats else None))
 
 
 def lbm_beta_from_nu(nu: float) -> float:

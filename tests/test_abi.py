@@ -127,3 +127,37 @@ def test_mixed_batches_are_rejected(L):
     with pytest.raises(L.LbmError):
         L.lbm_workspace_bytes([L.Domain()], L.Run(tile_h=65))
 
+
+# fake device addresses: these calls are refused on the host, before any
+# device call, so the pointers are never used
+F0, F1 = 1 << 20, 2 << 20
+
+
+@pytest.mark.parametrize("bad", [
+    dict(f0=0), dict(f1=0), dict(f1=F0), dict(n_steps=-1), dict(probe=(3, 3)),
+    dict(f_init=np.ones(9 * 32 * 16)), dict(beta=2.0), dict(storage=7),
+])
+def test_static_entry_refuses_bad_arguments_on_the_host(L, bad):
+    kw = dict(nx=32, ny=16, limiter=L.LBM_LIM_MEDIAN)
+    call = dict(f0=F0, f1=F1, n_steps=1, storage=L.LBM_F32)
+    for k in list(bad):
+        if k in call:
+            call[k] = bad.pop(k)
+    kw.update(bad)
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_step_static(L.Domain(**kw), call["storage"], call["f0"], call["f1"], call["n_steps"])
+    assert e.value.code == L.LBM_EINVAL
+
+
+def test_static_entry_refuses_domains_beyond_its_scratch(L):
+    """4096^2 FP32 with the median filter needs its Delta S' plane (64 MiB)
+    plus the work tables and partials: more than the static array."""
+    d = L.Domain(nx=4096, ny=4096, limiter=L.LBM_LIM_MEDIAN | L.LBM_LIM_TRIM, ds_form=L.LBM_DS_QUADRATIC)
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_step_static(d, L.LBM_F32, F0, F1, 1)
+    assert e.value.code == L.LBM_ENOMEM
+    assert str(L.LBM_STATIC_SCRATCH_BYTES) in str(e.value)
+    # the same grid with trimming alone needs no plane: only n_steps = 0 is
+    # safe to call without a GPU, and it is accepted
+    L.lbm_step_static(L.Domain(nx=4096, ny=4096, limiter=L.LBM_LIM_TRIM), L.LBM_F32, F0, F1, 0)
+    assert L.lib().lbm_step_static(None, 1, None, None, None, 1, None) == L.LBM_EINVAL
