@@ -130,7 +130,8 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT =
 #define LBM_RUN_RECORD 1u    /* keep per-node mask and Delta S' of every step */
 #define LBM_RUN_ENTROPY 2u   /* also accumulate sum S(f) (Sec. 4.3.1) */
 #define LBM_RUN_NO_GRAPH 4u  /* launch steps one by one (no captured graphs) */
-#define LBM_RUN_NO_TUNE 8u   /* accepted; the step kernels have a fixed shape */
+#define LBM_RUN_NO_TUNE 8u   /* no timing of shapes: narrow row blocks where a domain allows
+                                them, tile_h (or 64) for the second pass */
 
 /* One simulation domain.  All domains of one context share lattice, qe,
  * ds_form and bc (they run in the same kernel); sizes, beta, limiter and
@@ -176,9 +177,15 @@ typedef struct {
     int32_t device;             /* HIP device ordinal */
     int32_t stats_every;        /* >0: lbm_step synchronises every k steps and
                                    returns LBM_EUNSTABLE on non-finite moments */
-    int32_t tile_x, tile_y;     /* D2Q9 workgroups take 256 columns of one row
-                                   (one node per thread): pass 0 (or 256 and 1) */
-    int32_t tile_h;             /* rows per D2Q9 median/reduction tile (1..64); 0 = 64 */
+    int32_t tile_x;             /* D2Q9 collision row blocks (one node per thread, 256 per
+                                   workgroup): 256 = one row of 256 columns per workgroup;
+                                   64 = for a domain at most 128 wide, the narrowest of 64
+                                   or 128 columns that spans its rows, with 4 or 2 rows per
+                                   workgroup (wider domains keep 256); 0 = chosen by the
+                                   autotuner (see lbm_create) */
+    int32_t tile_y;             /* 0 (or 1) */
+    int32_t tile_h;             /* rows per D2Q9 second-pass tile (1..64); 0 = chosen by the
+                                   autotuner among 16, 32 and 64 (64 without a second pass) */
     uint32_t flags;             /* LBM_RUN_* */
     int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
     int32_t graph_chunk;        /* longest captured step sequence, 1..4096, 0 = 64: lbm_create
@@ -216,8 +223,16 @@ LBM_API int lbm_workspace_bytes(const lbm_domain_desc* domains, int32_t n_domain
 
 /* Create a context: validates the descriptors, allocates (or carves the
  * workspace into) population buffers, builds f(x, 0) (f_init, or f*(rho, u))
- * and the work tables.  Errors: EINVAL, ENOMEM, EDEVICE.  On error
- * *out is NULL and nothing is leaked. */
+ * and the work tables, and captures the step graphs.  D2Q9 autotuner: unless
+ * LBM_RUN_NO_TUNE or fixed by tile_x / tile_h, the candidate shapes (row
+ * blocks of 256 columns or narrow ones; second-pass tiles of 16, 32 or 64
+ * rows) are timed with HIP events on a few steps that all read the initial
+ * state (which they leave unchanged), and the fastest is kept; the choice is
+ * cached for the process under the descriptors, so later contexts of the
+ * same problem reuse it.  The shapes do not change the fields or E(Delta S');
+ * the FP64 sums the second pass adds to (limiter production) can differ in
+ * the last bits.  Errors: EINVAL, ENOMEM, EDEVICE.  On error *out is NULL and
+ * nothing is leaked. */
 LBM_API int lbm_create(const lbm_domain_desc* domains, int32_t n_domains,
                const lbm_run_desc* run, lbm_ctx** out);
 
@@ -252,8 +267,9 @@ LBM_API int lbm_limiter_mask(lbm_ctx* ctx, int32_t domain, uint8_t* mask, double
 LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples,
                     int64_t* n_written);
 
-/* Tile shape of the median pass and of the stats reduction: columns, 1, rows
- * (D1Q3: 254, 1, 1). */
+/* Shape in use.  D2Q9: columns of the first domain's collision row blocks
+ * (256, or 64 / 128 for a narrow domain), their rows per workgroup, and the
+ * rows of a second-pass tile.  D1Q3: 254, 1, 1. */
 LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
 
 /* sync; profiling aid outside the method.  Advances the state by n_steps

@@ -42,17 +42,18 @@ __global__ void k_finalize(StepArgs a, int parity_done, long long step)
     reduce_partials(a, parity_done, step, red);
 }
 
-// D2Q9: the partial of each tile is the sum of the collision partials of its
-// rows (row table index row_first + y strips + strip), in row order.
+// D2Q9: the set-0 partial of each group (kMaxTileH rows of one strip) is the
+// sum of the collision partials of its rows (index row_first + y strips +
+// strip), in row order.
 __global__ void __launch_bounds__(kThreads) k_tile_rows(StepArgs a, int parity_done)
 {
     __shared__ double red[4 * kNStat];
     __shared__ double rowbuf[kMaxTileH * kNStat + 8 * kNStat];
-    const Tile t = a.tiles[blockIdx.x];
+    const Tile t = a.groups[blockIdx.x];
     const DomainDev& D = a.dom[t.domain];
     const long long r0 = (long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads;
     const Acc none;
-    store_partial_rows(none, a.partials + ((long long)parity_done * 2 * a.ntiles + blockIdx.x) * kNStat, red,
+    store_partial_rows(none, a.partials + ((long long)parity_done * 2 * a.pstride + blockIdx.x) * kNStat, red,
                        a.rowpart + r0 * kNStat, t.y1 - t.y0, D.strips, rowbuf);
 }
 
@@ -425,7 +426,7 @@ hipError_t launch_budget(int storage, int bc, const StepArgs& a, hipStream_t s)
 hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s)
 {
     if (a.nrows > 0) {
-        hipLaunchKernelGGL(k_tile_rows, dim3(a.ntiles), dim3(kThreads), 0, s, a, a.parity);
+        hipLaunchKernelGGL(k_tile_rows, dim3(a.ngroups), dim3(kThreads), 0, s, a, a.parity);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -436,7 +437,7 @@ hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s)
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s)
 {
     if (a.nrows > 0) {
-        hipLaunchKernelGGL(k_tile_rows, dim3(a.ntiles), dim3(kThreads), 0, s, a, parity_done);
+        hipLaunchKernelGGL(k_tile_rows, dim3(a.ngroups), dim3(kThreads), 0, s, a, parity_done);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

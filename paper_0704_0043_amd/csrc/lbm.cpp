@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +27,7 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t kAlign = 256;
+constexpr int kMinTuneH = 16;   // smallest median-tile height the tuner tries
 
 // D2Q9 tiles: kThreads consecutive columns
 int strips_of(int nx) { return (nx + kThreads - 1) / kThreads; }
@@ -65,12 +68,13 @@ struct DomainHost {
     double shift = 0;
     int tile_first = 0, tile_count = 0;
     int row_first = 0, row_count = 0;
+    int group_first = 0, group_count = 0;
 };
 
 struct Layout {
     size_t off_dom = 0, off_tiles = 0, off_partials = 0, off_counter = 0, off_stage = 0, total = 0;
-    size_t off_rows = 0, off_rowpart = 0;
-    int max_tiles = 0, nrows = 0;
+    size_t off_rows = 0, off_rowpart = 0, off_groups = 0;
+    int max_tiles = 0, nrows = 0, ngroups = 0;
     size_t max_n = 0;
 };
 
@@ -103,12 +107,16 @@ struct lbm_ctx {
     std::vector<StepGraph> graphs[2];
     std::string err;
     std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
-    std::vector<Tile> rows_host;
+    std::vector<RowBlock> rows_host;
+    std::vector<Tile> groups_host;
+    int narrow = 1;             // row blocks of 64 / 128 columns for narrow domains
+    int tuned = 0;              // 1 when the tile shape was chosen by timing
     std::vector<DomainDev> dom_host;
 
     DomainDev* d_dom() const { return reinterpret_cast<DomainDev*>(ws + lay.off_dom); }
     Tile* d_tiles() const { return reinterpret_cast<Tile*>(ws + lay.off_tiles); }
-    Tile* d_rows() const { return reinterpret_cast<Tile*>(ws + lay.off_rows); }
+    RowBlock* d_rows() const { return reinterpret_cast<RowBlock*>(ws + lay.off_rows); }
+    Tile* d_groups() const { return reinterpret_cast<Tile*>(ws + lay.off_groups); }
     double* d_rowpart() const { return reinterpret_cast<double*>(ws + lay.off_rowpart); }
     double* d_partials() const { return reinterpret_cast<double*>(ws + lay.off_partials); }
     long long* d_counter() const { return reinterpret_cast<long long*>(ws + lay.off_counter); }
@@ -138,8 +146,8 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
     if (!doms || nd < 1 || !run) return fail(nullptr, LBM_EINVAL, "domains/run must be non-NULL, n_domains >= 1");
     if (run->struct_size < sizeof(lbm_run_desc)) return fail(nullptr, LBM_EINVAL, "lbm_run_desc.struct_size too small");
     if (run->storage < LBM_F64 || run->storage > LBM_BF16_SHIFT) return fail(nullptr, LBM_EINVAL, "bad storage");
-    if (run->tile_x != 0 && run->tile_x != kThreads)
-        return fail(nullptr, LBM_EINVAL, "tile_x must be 0 or 256 (columns of one tile)");
+    if (run->tile_x != 0 && run->tile_x != kWave && run->tile_x != kThreads)
+        return fail(nullptr, LBM_EINVAL, "tile_x must be 0 (tuned), 64 (narrow row blocks) or 256");
     if (run->tile_y != 0 && run->tile_y != 1) return fail(nullptr, LBM_EINVAL, "tile_y must be 0 or 1");
     if (run->tile_h < 0 || run->tile_h > kMaxTileH) return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 64]");
     if (run->graph_chunk < 0 || run->graph_chunk > 4096)
@@ -270,6 +278,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     size_t off = 0;
     L.max_tiles = 0;
     L.nrows = 0;
+    L.ngroups = 0;
     L.max_n = 0;
     dh.resize(nd);
     for (int k = 0; k < nd; ++k) {
@@ -295,9 +304,11 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
             off = align_up(off + size_t(cap) * 2 * sizeof(float), kAlign);
         }
         off = plan_extras(h, storage, off);
-        const int min_h = run->tile_h > 0 ? run->tile_h : kMaxTileH;
+        // the tile table is sized for the smallest height the tuner may pick
+        const int min_h = run->tile_h > 0 ? run->tile_h : kMinTuneH;
         const int tiles = tiles_of(h.d.lattice, h.d.nx, h.d.ny, min_h);
         L.max_tiles += tiles;
+        L.ngroups += tiles_of(h.d.lattice, h.d.nx, h.d.ny, kMaxTileH);
         if (h.d.lattice == LBM_D2Q9) L.nrows += strips_of(h.d.nx) * h.d.ny;
         L.max_n = std::max(L.max_n, h.n);
     }
@@ -305,10 +316,12 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     off = align_up(off + nd * sizeof(DomainDev), kAlign);
     L.off_tiles = off;
     off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
+    L.off_groups = off;
+    off = align_up(off + L.ngroups * sizeof(Tile), kAlign);
     L.off_partials = off;
     off = align_up(off + size_t(4) * L.max_tiles * kNStat * sizeof(double), kAlign);
     L.off_rows = off;
-    off = align_up(off + size_t(L.nrows) * sizeof(Tile), kAlign);
+    off = align_up(off + size_t(L.nrows) * sizeof(RowBlock), kAlign);
     L.off_rowpart = off;
     off = align_up(off + size_t(L.nrows) * kNStat * sizeof(double), kAlign);
     L.off_counter = off;
@@ -339,18 +352,51 @@ std::vector<Tile> build_tiles(lbm_ctx* ctx, int th)
     return spatial;
 }
 
-// D2Q9 row segments of kThreads columns, row-major within each domain: the
-// collision kernel runs one workgroup per segment in this order.
-void build_rows(lbm_ctx* ctx)
+// D2Q9 row blocks, row-major within each domain: the collision kernel runs
+// one workgroup per block in this order.  Every domain row has one collision
+// partial per 256-column strip (row_first + y strips + strip), whatever the
+// blocks; `narrow` gives narrow domains blocks of several rows.
+void build_rows(lbm_ctx* ctx, int narrow)
 {
     ctx->rows_host.clear();
+    ctx->narrow = narrow;
     if (ctx->lattice != LBM_D2Q9) return;
+    int part = 0;
     for (size_t k = 0; k < ctx->dom.size(); ++k) {
         DomainHost& h = ctx->dom[k];
-        h.row_first = int(ctx->rows_host.size());
+        h.row_first = part;
         h.row_count = strips_of(h.d.nx) * h.d.ny;
-        for (int i = 0; i < h.row_count; ++i) ctx->rows_host.push_back(row_entry2d(int(k), h.d.nx, i));
+        part += h.row_count;
+        const int width = seg_width(h.d.nx, narrow);
+        const int nb = blocks_of(h.d.nx, h.d.ny, width);
+        for (int i = 0; i < nb; ++i) ctx->rows_host.push_back(block_entry2d(int(k), h.d.nx, h.d.ny, width, i));
     }
+}
+
+// The groups of kMaxTileH rows whose collision partials are summed together
+// for the stats and E(Delta S'), fixed so that those sums do not depend on
+// the tile height in use (D1Q3: its tiles).
+void build_groups(lbm_ctx* ctx)
+{
+    ctx->groups_host.clear();
+    for (size_t k = 0; k < ctx->dom.size(); ++k) {
+        DomainHost& h = ctx->dom[k];
+        h.group_first = int(ctx->groups_host.size());
+        const int nx = h.d.nx, ny = h.d.ny;
+        const int count = tiles_of(ctx->lattice, nx, ny, kMaxTileH);
+        for (int i = 0; i < count; ++i)
+            ctx->groups_host.push_back(ctx->lattice == LBM_D2Q9 ? tile_entry2d(int(k), nx, ny, kMaxTileH, i)
+                                                                : tile_entry1d(int(k), nx, i));
+        h.group_count = count;
+    }
+}
+
+int upload_rows(lbm_ctx* ctx)
+{
+    if (ctx->rows_host.empty()) return LBM_OK;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_rows(), ctx->rows_host.data(), ctx->rows_host.size() * sizeof(RowBlock),
+                                hipMemcpyHostToDevice, ctx->stream));
+    return LBM_OK;
 }
 
 // Device view of one domain: device pointers into `base` at the host
@@ -382,6 +428,8 @@ DomainDev make_dev(const DomainHost& h, char* base, void* b0, void* b1, int prob
     d.strips = strips_of(h.d.nx);
     d.row_first = h.row_first;
     d.row_count = h.row_count;
+    d.group_first = h.group_first;
+    d.group_count = h.group_count;
     d.stats = reinterpret_cast<double*>(base + h.off_stats);
     d.dsbuf = h.dsbuf ? base + h.off_dsbuf : nullptr;
     d.phibuf = h.phibuf ? base + h.off_phibuf : nullptr;
@@ -438,7 +486,10 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.ens_pass = ctx->ens_pass ? 1 : 0;
     a.budget = ctx->budget ? 1 : 0;
     a.rows = ctx->d_rows();
-    a.nrows = ctx->lay.nrows;
+    a.nrows = int(ctx->rows_host.size());
+    a.groups = ctx->d_groups();
+    a.ngroups = ctx->lay.ngroups;
+    a.pstride = ctx->lay.max_tiles;
     a.rowpart = ctx->d_rowpart();
     a.parity = parity;
     a.flags = ctx->flags & (LBM_RUN_RECORD | LBM_RUN_ENTROPY);
@@ -485,9 +536,11 @@ StepKind step_kind(const lbm_ctx* ctx)
                     ctx->ens_pass, ctx->budget};
 }
 
-int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr)
+int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr, unsigned extra_flags = 0)
 {
-    const hipError_t e = launch_step(step_kind(ctx), step_args(ctx, parity), ctx->stream, ev);
+    StepArgs a = step_args(ctx, parity);
+    a.flags |= extra_flags;
+    const hipError_t e = launch_step(step_kind(ctx), a, ctx->stream, ev);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return LBM_OK;
 }
@@ -512,11 +565,115 @@ void drop_graphs(lbm_ctx* ctx)
     }
 }
 
-// The step kernels work on row segments of kThreads columns; D2Q9 tiles only
-// group rows for the reduction of the stats (and fix its summation order).
-int autotune(lbm_ctx* ctx, int fixed_th)
+// ---- autotuner ---------------------------------------------------------------
+// Two shape choices change the speed of a D2Q9 step and nothing it computes:
+// the row blocks of the collision kernel (256 columns per row, or several rows
+// of a narrow domain per workgroup) and the height of the tiles the second pass
+// walks (the stats partials are grouped by fixed 64-row groups, so E(Delta S')
+// and every field come out the same for any height; only the FP64 sums that
+// the second pass adds to may differ in the last bits).  lbm_create times the
+// candidate shapes on the live state with HIP events and keeps the fastest; a
+// process-wide cache keyed by the descriptors gives the same choice to every
+// later context of the same problem.
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;   // key -> (narrow, tile height)
+
+std::string tune_key(const lbm_ctx* ctx)
 {
-    return set_tiles(ctx, fixed_th ? fixed_th : kMaxTileH);
+    std::string k = std::to_string(ctx->device) + "/" + std::to_string(ctx->storage) + "/" + std::to_string(ctx->qe) +
+                    "/" + std::to_string(ctx->ds) + "/" + std::to_string(ctx->bc) + "/" + std::to_string(ctx->elbm) +
+                    "/" + std::to_string(ctx->flags & (LBM_RUN_RECORD | LBM_RUN_ENTROPY));
+    for (const auto& h : ctx->dom)
+        k += ";" + std::to_string(h.d.nx) + "x" + std::to_string(h.d.ny) + ":" + std::to_string(h.d.limiter) + ":" +
+             std::to_string(h.d.median_mode) + ":" + std::to_string(h.d.homothety) + ":" +
+             std::to_string(h.d.top_k > 0) + ":" + std::to_string(h.d.bc);
+    return k;
+}
+
+int apply_shape(lbm_ctx* ctx, int narrow, int th)
+{
+    build_rows(ctx, narrow);
+    int rc = upload_rows(ctx);
+    return rc ? rc : set_tiles(ctx, th);
+}
+
+// average milliseconds of `n` steps that all read buffer 0 (the initial state
+// stays intact; buffer 1 and the scratch arrays are overwritten)
+int time_shape(lbm_ctx* ctx, int n, double& ms, unsigned extra_flags = 0)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = LBM_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(ctx, LBM_EDEVICE, "event");
+    if (!rc) rc = launch_one(ctx, 0, nullptr, extra_flags);   // untimed: first launch of this shape
+    if (!rc && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = fail(ctx, LBM_EDEVICE, "event record");
+    for (int k = 0; k < n && !rc; ++k) rc = launch_one(ctx, 0, nullptr, extra_flags);
+    float t = 0;
+    if (!rc && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        rc = fail(ctx, LBM_EDEVICE, "event timing");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ms = double(t) / n;
+    return rc;
+}
+
+int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
+{
+    bool any_narrow = false;
+    for (const auto& h : ctx->dom) any_narrow = any_narrow || seg_width(h.d.nx, 1) < kThreads;
+    std::vector<int> widths;
+    if (run->tile_x == kThreads || !any_narrow) widths = {0};
+    else if (run->tile_x == kWave) widths = {1};
+    else widths = {1, 0};
+    std::vector<int> heights;
+    if (run->tile_h > 0) heights = {run->tile_h};
+    else if (ctx->median_pass || ctx->ens_pass) heights = {16, 32, 64};
+    else heights = {kMaxTileH};
+    ctx->tuned = 0;
+    if ((ctx->flags & LBM_RUN_NO_TUNE) || widths.size() * heights.size() == 1)
+        return apply_shape(ctx, widths[0], heights.back());
+    const std::string key = tune_key(ctx);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            ctx->tuned = 1;
+            return apply_shape(ctx, it->second.first, it->second.second);
+        }
+    }
+    // Warm the part up on the default shape, then time every candidate in two
+    // rounds (the second in reverse order) and keep each one's best.  How
+    // much of the second pass has work depends on the flow (at the start
+    // often no tile has a candidate); a candidate is scored by the sum of a
+    // step as it stands and a step whose second pass walks every tile.
+    const bool second = ctx->median_pass || ctx->ens_pass;
+    int rc = apply_shape(ctx, widths[0], heights.back());
+    double ms = 0;
+    if (!rc) rc = time_shape(ctx, 8, ms);
+    std::vector<std::pair<int, int>> cand;
+    for (int w : widths)
+        for (int th : heights) cand.push_back({w, th});
+    std::vector<double> best(cand.size(), 1e30), best_all(cand.size(), second ? 1e30 : 0.0);
+    for (int round = 0; round < 2 && !rc; ++round)
+        for (size_t j = 0; j < cand.size() && !rc; ++j) {
+            const size_t c = round ? cand.size() - 1 - j : j;
+            rc = apply_shape(ctx, cand[c].first, cand[c].second);
+            if (!rc) rc = time_shape(ctx, 3, ms);
+            if (!rc) best[c] = std::min(best[c], ms);
+            if (!rc && second) rc = time_shape(ctx, 3, ms, kFlagAllTiles);
+            if (!rc && second) best_all[c] = std::min(best_all[c], ms);
+        }
+    if (rc) return rc;
+    size_t pick = 0;
+    for (size_t c = 1; c < cand.size(); ++c)
+        if (best[c] + best_all[c] < best[pick] + best_all[pick]) pick = c;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = cand[pick];
+    }
+    ctx->tuned = 1;
+    return apply_shape(ctx, cand[pick].first, cand[pick].second);
 }
 
 // Capture `len` steps starting at `parity` into one executable graph.
@@ -626,7 +783,7 @@ int read_stats(lbm_ctx* ctx, int32_t d, lbm_entropy_stats_t* out)
 // domain, tight planes (plane = nx ny), no record planes, no probe.
 struct StaticLayout {
     size_t off_dom = 0, off_tiles = 0, off_rows = 0, off_partials = 0, off_rowpart = 0, off_counter = 0, total = 0;
-    int ntiles = 0, nrows = 0;
+    int ntiles = 0, nblocks = 0, nparts = 0;
 };
 
 void plan_static(const lbm_domain_desc& d, int storage, DomainHost& h, StaticLayout& L)
@@ -637,23 +794,27 @@ void plan_static(const lbm_domain_desc& d, int storage, DomainHost& h, StaticLay
     h.n = size_t(d.nx) * d.ny;
     h.plane = (long long)h.n;
     h.shift = storage == LBM_F64 ? 0.0 : d.rho0;
+    // tiles of kMaxTileH rows, which are also the stats groups; narrow row blocks
     L.ntiles = tiles_of(d.lattice, d.nx, d.ny, kMaxTileH);
-    L.nrows = d.lattice == LBM_D2Q9 ? strips_of(d.nx) * d.ny : 0;
+    L.nblocks = d.lattice == LBM_D2Q9 ? blocks_of(d.nx, d.ny, seg_width(d.nx, 1)) : 0;
+    L.nparts = d.lattice == LBM_D2Q9 ? strips_of(d.nx) * d.ny : 0;
     h.tile_first = 0;
     h.tile_count = L.ntiles;
+    h.group_first = 0;
+    h.group_count = L.ntiles;
     h.row_first = 0;
-    h.row_count = L.nrows;
+    h.row_count = L.nparts;
     size_t off = 0;
     L.off_dom = off;
     off = align_up(off + sizeof(DomainDev), kAlign);
     L.off_tiles = off;
     off = align_up(off + size_t(L.ntiles) * sizeof(Tile), kAlign);
     L.off_rows = off;
-    off = align_up(off + size_t(L.nrows) * sizeof(Tile), kAlign);
+    off = align_up(off + size_t(L.nblocks) * sizeof(RowBlock), kAlign);
     L.off_partials = off;
     off = align_up(off + size_t(4) * L.ntiles * kNStat * sizeof(double), kAlign);
     L.off_rowpart = off;
-    off = align_up(off + size_t(L.nrows) * kNStat * sizeof(double), kAlign);
+    off = align_up(off + size_t(L.nparts) * kNStat * sizeof(double), kAlign);
     L.off_counter = off;
     off = align_up(off + 2 * sizeof(long long), kAlign);
     L.total = plan_extras(h, storage, off);
@@ -799,15 +960,15 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("init: ") + hipGetErrorString(e)));
     }
-    build_rows(ctx);
-    if (int(ctx->rows_host.size()) != ctx->lay.nrows)
-        return bail(fail(nullptr, LBM_EINVAL, "row table size mismatch"));
-    if (!ctx->rows_host.empty()) {
-        e = hipMemcpyAsync(ctx->d_rows(), ctx->rows_host.data(), ctx->rows_host.size() * sizeof(Tile),
-                           hipMemcpyHostToDevice, ctx->stream);
-        if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("rows: ") + hipGetErrorString(e)));
-    }
-    rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run->tile_h) : set_tiles(ctx, 1);
+    build_groups(ctx);
+    if (int(ctx->groups_host.size()) != ctx->lay.ngroups)
+        return bail(fail(nullptr, LBM_EINVAL, "group table size mismatch"));
+    e = hipMemcpyAsync(ctx->d_groups(), ctx->groups_host.data(), ctx->groups_host.size() * sizeof(Tile),
+                       hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("groups: ") + hipGetErrorString(e)));
+    // the tuner runs steps: the step counters must hold valid indices first
+    rc = reset_counters(ctx);
+    if (!rc) rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run) : apply_shape(ctx, 0, 1);
     if (rc) {
         g_err = ctx->err;
         return bail(rc);
@@ -974,8 +1135,12 @@ int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_
 {
     if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL context");
     const bool d2 = ctx->lattice == LBM_D2Q9;
-    if (tile_x) *tile_x = d2 ? kThreads : k1DWidth;
-    if (tile_y) *tile_y = 1;
+    // D2Q9: columns of the first domain's row blocks (256, or 64 / 128 for a
+    // narrow domain), their rows per workgroup, and the second pass's tile
+    // height; D1Q3: sites per workgroup, 1, 1
+    const int width = d2 ? seg_width(ctx->dom[0].d.nx, ctx->narrow) : k1DWidth;
+    if (tile_x) *tile_x = width;
+    if (tile_y) *tile_y = d2 ? kThreads / width : 1;
     if (tile_h) *tile_h = d2 ? ctx->th : 1;
     return LBM_OK;
 }
@@ -1051,9 +1216,9 @@ int lbm_step_static(const lbm_domain_desc* domain, int32_t storage, void* stream
     const DomainDev dd = make_dev(h, base, f0, f1, 1, 0);
     DomainDev* dom = reinterpret_cast<DomainDev*>(base + L.off_dom);
     Tile* tiles = reinterpret_cast<Tile*>(base + L.off_tiles);
-    Tile* rows = reinterpret_cast<Tile*>(base + L.off_rows);
+    RowBlock* rows = reinterpret_cast<RowBlock*>(base + L.off_rows);
     long long* counter = reinterpret_cast<long long*>(base + L.off_counter);
-    e = launch_static_setup(dd, domain->lattice, dom, tiles, L.ntiles, rows, L.nrows, kMaxTileH, counter, s);
+    e = launch_static_setup(dd, domain->lattice, dom, tiles, L.ntiles, rows, L.nblocks, counter, s);
     if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, std::string("static setup: ") + hipGetErrorString(e));
     StepKind k;
     k.storage = storage;
@@ -1077,7 +1242,10 @@ int lbm_step_static(const lbm_domain_desc* domain, int32_t storage, void* stream
     a.ens_pass = k.ens_pass ? 1 : 0;
     a.budget = k.budget ? 1 : 0;
     a.rows = rows;
-    a.nrows = L.nrows;
+    a.nrows = L.nblocks;
+    a.groups = tiles;
+    a.ngroups = L.ntiles;
+    a.pstride = L.ntiles;
     a.rowpart = reinterpret_cast<double*>(base + L.off_rowpart);
     a.counter = counter;
     for (int64_t t = 0; t < n_steps && e == hipSuccess; ++t) {

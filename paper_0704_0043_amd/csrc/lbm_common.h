@@ -21,7 +21,9 @@ enum { kLBGK = 0, kELBM = 1 };
 enum { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 enum : unsigned { kMaskTrim = 1, kMaskMedian = 2, kMaskNonpos = 4, kMaskNotFluid = 8, kMaskEns = 16, kMaskPos = 32 };
-enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2 };
+// kFlagAllTiles makes the second pass walk every tile, as if each had a
+// candidate; only the tuner sets it, to time that pass's full work.
+enum : unsigned { kFlagRecord = 1, kFlagEntropy = 2, kFlagAllTiles = 4 };
 
 constexpr int kThreads = 256;      // workgroup size of the step kernels (= D2Q9 tile width)
 constexpr int kWave = 64;          // wavefront size (CDNA)
@@ -96,7 +98,8 @@ struct DomainDev {
     double* ens;                  // [kNEns]: E(Delta S') and the thresholds of this step
     void* phibuf;                 // D1Q3 with ensemble limiters: phi applied by the first pass
     int strips;                   // D2Q9: column strips of kThreads columns
-    int row_first, row_count;     // D2Q9: this domain's range in the row table
+    int row_first, row_count;     // D2Q9: this domain's range of row partials (one per row and strip)
+    int group_first, group_count; // this domain's range of collision-partial groups (kMaxTileH rows)
     BudgetState* bstate;          // budget threshold: search state (budget limiter only)
     BudgetBucket* bhist;          // [kBudgetBuckets], left zero between levels
     double* stats;          // [kNStat + 1]: last finalised sums, then the step index
@@ -128,10 +131,24 @@ struct Tile {
 
 constexpr int k1DWidth = kThreads - 2;   // output sites of one D1Q3 workgroup
 
+// One D2Q9 collision workgroup: rows [y0, y1) by columns [x0, x1) of one
+// domain, `width` (64, 128 or 256) columns per row, kThreads / width rows.
+struct RowBlock {
+    int domain, x0, x1, y0, y1, width;
+};
+
+// Columns of a domain's row blocks: with `narrow`, the narrowest of 64, 128
+// and 256 that spans a row of a narrow domain (several of its rows then share
+// a workgroup and fewer lanes idle), else 256.
+__host__ __device__ inline int seg_width(int nx, int narrow)
+{
+    return (narrow && nx <= 64) ? 64 : ((narrow && nx <= 128) ? 128 : kThreads);
+}
+
 // Entry i of a domain's work tables (host and device build them alike):
 // D2Q9 tiles of kThreads columns by th rows in spatial order (row chunk, then
-// column strip); D2Q9 row segments of kThreads columns in row-major order;
-// D1Q3 tiles of k1DWidth sites.
+// column strip); D2Q9 row blocks in row-major order; D1Q3 tiles of k1DWidth
+// sites.
 __host__ __device__ inline Tile tile_entry2d(int domain, int nx, int ny, int th, int i)
 {
     const int strips = (nx + kThreads - 1) / kThreads;
@@ -140,11 +157,16 @@ __host__ __device__ inline Tile tile_entry2d(int domain, int nx, int ny, int th,
     return Tile{domain, x0, x0 + kThreads < nx ? x0 + kThreads : nx, r * th, r * th + th < ny ? r * th + th : ny,
                 r, chunks, (ny - r + chunks - 1) / chunks};
 }
-__host__ __device__ inline Tile row_entry2d(int domain, int nx, int i)
+__host__ __device__ inline int blocks_of(int nx, int ny, int width)
 {
-    const int strips = (nx + kThreads - 1) / kThreads;
-    const int y = i / strips, x0 = (i - y * strips) * kThreads;
-    return Tile{domain, x0, x0 + kThreads < nx ? x0 + kThreads : nx, y, y + 1, y, 1, 1};
+    const int rows = kThreads / width;
+    return ((nx + width - 1) / width) * ((ny + rows - 1) / rows);
+}
+__host__ __device__ inline RowBlock block_entry2d(int domain, int nx, int ny, int width, int i)
+{
+    const int cols = (nx + width - 1) / width, rows = kThreads / width;
+    const int r = i / cols, x0 = (i - r * cols) * width, y0 = r * rows;
+    return RowBlock{domain, x0, x0 + width < nx ? x0 + width : nx, y0, y0 + rows < ny ? y0 + rows : ny, width};
 }
 __host__ __device__ inline Tile tile_entry1d(int domain, int nx, int i)
 {
@@ -163,14 +185,20 @@ struct StepArgs {
     int ndomains;
     int parity;             // read buf[parity], write buf[1 - parity]
     unsigned flags;
-    double* partials;       // [2 parities][2 sets][ntiles][kNStat]: FP64 stats of each tile
-                            // (set 0: collision, set 1: median pass)
+    double* partials;       // [2 parities][2 sets][pstride][kNStat]: FP64 stats, set 0 (collision)
+                            // per group of kMaxTileH rows, set 1 (second pass) per tile
+    const Tile* groups;     // the collision-partial groups: tiles of kMaxTileH rows, fixed, so
+                            // that the set-0 sums (and E(Delta S')) do not depend on the tile
+                            // height; D1Q3: the tiles
+    int ngroups;
+    int pstride;            // slots per set in `partials` (>= ntiles, ngroups)
     int median_pass;        // 1 if a second pass (median and/or ensemble limiters) writes set 1
     int ens_pass;           // 1 if some domain has an ensemble-dependent limiter
     int budget;             // 1 if some domain has the budget threshold
-    const Tile* rows;       // D2Q9 row segments in row-major order, one per collision workgroup
+    const RowBlock* rows;   // D2Q9 row blocks in row-major order, one per collision workgroup
     int nrows;              // the D2Q9 collision grid has nrows blocks
-    double* rowpart;        // [nrows][kNStat]: collision partials of the last step
+    double* rowpart;        // [rows x strips][kNStat]: collision partials of the last step, one
+                            // per domain row and 256-column strip
     long long* counter;     // [2] step index by parity
 };
 
@@ -179,8 +207,8 @@ struct StepArgs {
 constexpr size_t kStaticScratchBytes = LBM_STATIC_SCRATCH_BYTES;
 // its address on `device` (looked up once per device; `device` must be current)
 hipError_t static_scratch(int device, char** ptr);
-hipError_t launch_static_setup(const DomainDev& dd, int lattice, DomainDev* dom, Tile* tiles, int ntiles, Tile* rows,
-                               int nrows, int th, long long* counter, hipStream_t s);
+hipError_t launch_static_setup(const DomainDev& dd, int lattice, DomainDev* dom, Tile* tiles, int ntiles,
+                               RowBlock* rows, int nrows, long long* counter, hipStream_t s);
 hipError_t launch_static_stats(const DomainDev* dom, double shift_mass, double* out, hipStream_t s);
 
 // Launchers (one per storage type / lattice), defined in the .hip files.

@@ -741,10 +741,14 @@ __device__ __forceinline__ A limiter_phi(A dpost, bool has_med, A med, const Dom
 // Per-thread running sums over the (at most 64) nodes a thread visits, kept
 // in type S: FP64 in FP64 mode, FP32 in the reduced-storage modes (a
 // 64-term FP32 sum of FP32 site values loses nothing that matters); the
-// workgroup, tile, domain and global reductions are FP64.
-template <class S>
+// workgroup, tile, domain and global reductions are FP64.  The second D2Q9
+// pass keeps the limiter's entropy production in FP64 (type SL): a thread
+// there sums over a tile's column, whose height is a launch choice, and in
+// FP64 that choice changes the sum only at FP64 rounding.
+template <class S, class SL = S>
 struct AccT {
-    S mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, lim = 0, ent = 0, maxd = 0;
+    S mass = 0, jx = 0, jy = 0, dpre = 0, dpost = 0, ent = 0, maxd = 0;
+    SL lim = 0;
     int trim = 0, filt = 0, nonpos = 0, nonfin = 0, fluid = 0, above = 0, ens = 0, pos = 0;
 
     __device__ void moments(const SiteScalars& s)
@@ -771,8 +775,8 @@ using Acc = AccT<double>;
 
 // Deterministic workgroup reduction of the accumulators into one partial
 // (fixed butterfly inside each wave, then waves in order).
-template <class S>
-__device__ inline void store_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */)
+template <class S, class SL>
+__device__ inline void store_partial(const AccT<S, SL>& acc, double* out, double* lds /* [4 * kNStat] */)
 {
     double v[kNStat] = {double(acc.mass), double(acc.jx), double(acc.jy), double(acc.dpre), double(acc.dpost),
                         double(acc.maxd), double(acc.lim), double(acc.ent), double(acc.trim), double(acc.filt),
@@ -854,12 +858,16 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
     }
 }
 
-// Partial of a workgroup whose threads hold at most one node each: the
-// sums (FP32 for reduced storage, FP64 for FP64 storage) by a fixed xor
-// butterfly in each wave, the 0/1 counts by ballots, the waves combined in
-// FP64 in order.
+// Partials of a workgroup whose threads hold at most one node each, covering
+// `nrow` rows of `wpr` waves each (a row of 64 wpr columns): the sums (FP32
+// for reduced storage, FP64 for FP64 storage) by a fixed xor butterfly in
+// each wave, the 0/1 counts by ballots; then for each row its waves combined
+// in FP64 in order, written to out + r * stride (r < nrow).  kSAbove is a
+// bit mask there: bit w is set when wave w of the row holds a node above the
+// median tolerance (the median pass reads which waves stored Delta S').
 template <class S>
-__device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds /* [4 * kNStat] */)
+__device__ inline void node_partial_rows(const AccT<S>& acc, double* out, long long stride, int wpr, int nrow,
+                                         double* lds /* [4 * kNStat] */)
 {
     S v[8] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent};
 #pragma unroll
@@ -872,11 +880,10 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
     }
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
-    // kSAbove is not a count here: bit w is set when wave w holds a node above
-    // the median tolerance (the median pass reads which waves stored Delta S')
     const double cnt[8] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
                            double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
-                           double(__popcll(__ballot(acc.fluid != 0))), __ballot(acc.above != 0) ? double(1 << wave) : 0.0,
+                           double(__popcll(__ballot(acc.fluid != 0))),
+                           __ballot(acc.above != 0) ? double(1 << (wave % wpr)) : 0.0,
                            double(__popcll(__ballot(acc.ens != 0))), double(__popcll(__ballot(acc.pos != 0)))};
     if (lane == 0) {
 #pragma unroll
@@ -885,11 +892,12 @@ __device__ inline void node_partial(const AccT<S>& acc, double* out, double* lds
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + 8 + k] = cnt[k];
     }
     __syncthreads();
-    if (tid < kNStat) {
-        const int nw = (blockDim.x * blockDim.y) >> 6;
-        double s = lds[tid];
-        for (int w = 1; w < nw; ++w) s = (tid == kSMax) ? fmax(s, lds[w * kNStat + tid]) : s + lds[w * kNStat + tid];
-        out[tid] = s;
+    if (tid < nrow * kNStat) {
+        const int r = tid / kNStat, k = tid - r * kNStat;
+        const double* row = lds + r * wpr * kNStat;
+        double s = row[k];
+        for (int w = 1; w < wpr; ++w) s = (k == kSMax) ? fmax(s, row[w * kNStat + k]) : s + row[w * kNStat + k];
+        out[r * stride * kNStat + k] = s;
     }
 }
 
@@ -1017,23 +1025,27 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
 {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthr = blockDim.x * blockDim.y;
-    // set 0: collision partials (D2Q9: summed from the rows on demand); set 1:
-    // the median pass, when it ran
-    const double* part = a.partials + (long long)parity * 2 * a.ntiles * kNStat;
+    // set 0: collision partials per group (D2Q9: summed from the rows on
+    // demand); set 1: the second pass per tile, when it ran
+    const double* part = a.partials + (long long)parity * 2 * a.pstride * kNStat;
     const int nsets = a.median_pass ? 2 : 1;
-    // domains with few tiles: one thread each, tiles summed in order
+    // domains with few slots: one thread each, slots summed in order
     for (int d = tid; d < a.ndomains; d += nthr) {
         const DomainDev& D = a.dom[d];
-        if (D.tile_count > kSmallDomainTiles) continue;
+        // the rule depends on the groups only, so that set 0 is summed in the
+        // same order whatever the tile height (set 1 adds zeros to its slots)
+        if (D.group_count > kSmallDomainTiles) continue;
         double v[kNStat];
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) v[k] = 0;
-        for (int set = 0; set < nsets; ++set)
-            for (int t = 0; t < D.tile_count; ++t) {
-                const double* p = part + ((long long)set * a.ntiles + D.tile_first + t) * kNStat;
+        for (int set = 0; set < nsets; ++set) {
+            const int first = set ? D.tile_first : D.group_first, count = set ? D.tile_count : D.group_count;
+            for (int t = 0; t < count; ++t) {
+                const double* p = part + ((long long)set * a.pstride + first + t) * kNStat;
 #pragma unroll
                 for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
             }
+        }
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) D.stats[k] = v[k];
         D.stats[kNStat] = double(step);
@@ -1041,16 +1053,18 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
     // large domains: the whole workgroup, fixed slices then a fixed tree
     for (int d = 0; d < a.ndomains; ++d) {
         const DomainDev& D = a.dom[d];
-        if (D.tile_count <= kSmallDomainTiles) continue;
+        if (D.group_count <= kSmallDomainTiles) continue;
         double v[kNStat];
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) v[k] = 0;
-        for (int set = 0; set < nsets; ++set)
-            for (int t = tid; t < D.tile_count; t += nthr) {
-                const double* p = part + ((long long)set * a.ntiles + D.tile_first + t) * kNStat;
+        for (int set = 0; set < nsets; ++set) {
+            const int first = set ? D.tile_first : D.group_first, count = set ? D.tile_count : D.group_count;
+            for (int t = tid; t < count; t += nthr) {
+                const double* p = part + ((long long)set * a.pstride + first + t) * kNStat;
 #pragma unroll
                 for (int k = 0; k < kNStat; ++k) v[k] = (k == kSMax) ? fmax(v[k], p[k]) : v[k] + p[k];
             }
+        }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll

@@ -42,9 +42,9 @@ hipError_t static_scratch(int device, char** ptr)
 // builds them for a context) and clears what a run must start from: the
 // step counters, the stats and the selection histogram.
 __global__ void __launch_bounds__(kThreads) k_static_setup(DomainDev dd, int lattice, DomainDev* dom, Tile* tiles,
-                                                           int ntiles, Tile* rows, int nrows, int th,
-                                                           long long* counter)
+                                                           int ntiles, RowBlock* rows, int nrows, long long* counter)
 {
+    const int width = seg_width(dd.nx, 1);
     const int nb = dd.bhist ? kBudgetBuckets : 0;
     const int n = max(max(ntiles, nrows), max(nb, kNStat + 1));
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -55,8 +55,8 @@ __global__ void __launch_bounds__(kThreads) k_static_setup(DomainDev dd, int lat
         }
         if (i <= kNStat) dd.stats[i] = 0.0;
         if (i < ntiles)
-            tiles[i] = lattice == kD2Q9 ? tile_entry2d(0, dd.nx, dd.ny, th, i) : tile_entry1d(0, dd.nx, i);
-        if (i < nrows) rows[i] = row_entry2d(0, dd.nx, i);
+            tiles[i] = lattice == kD2Q9 ? tile_entry2d(0, dd.nx, dd.ny, kMaxTileH, i) : tile_entry1d(0, dd.nx, i);
+        if (i < nrows) rows[i] = block_entry2d(0, dd.nx, dd.ny, width, i);
         if (i < nb) dd.bhist[i] = BudgetBucket{0, 0, 0};
     }
 }
@@ -85,13 +85,13 @@ __global__ void k_static_stats(const DomainDev* dom, double shift_mass, double* 
     out[13] = s[kSPos];
 }
 
-hipError_t launch_static_setup(const DomainDev& dd, int lattice, DomainDev* dom, Tile* tiles, int ntiles, Tile* rows,
-                               int nrows, int th, long long* counter, hipStream_t s)
+hipError_t launch_static_setup(const DomainDev& dd, int lattice, DomainDev* dom, Tile* tiles, int ntiles,
+                               RowBlock* rows, int nrows, long long* counter, hipStream_t s)
 {
     const int n = std::max(std::max(ntiles, nrows), std::max(kBudgetBuckets, kNStat + 1));
     const int blocks = std::min((n + kThreads - 1) / kThreads, 1024);
     hipLaunchKernelGGL(k_static_setup, dim3(blocks), dim3(kThreads), 0, s, dd, lattice, dom, tiles, ntiles, rows,
-                       nrows, th, counter);
+                       nrows, counter);
     return hipGetLastError();
 }
 

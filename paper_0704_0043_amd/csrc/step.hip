@@ -83,7 +83,7 @@ __device__ inline int tile_of_block(const StepArgs& a, int first)
 // kernel writes it directly), set 1 = median pass
 __device__ inline double* partial_slot(const StepArgs& a, int set, int tile)
 {
-    return a.partials + (((long long)a.parity * 2 + set) * a.ntiles + tile) * kNStat;
+    return a.partials + (((long long)a.parity * 2 + set) * a.pstride + tile) * kNStat;
 }
 
 // trimming factor of one node (it depends on the node alone, Sec. 3.2/3.4)
@@ -198,11 +198,12 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     using L = Lat<kD2Q9>;
     constexpr int Q = 9;
     __shared__ double red[4 * kNStat];
-    // one row segment per workgroup, in row-major order: the grid streams
+    // one row block per workgroup, in row-major order: the grid streams
     // through the domain a few rows at a time (DRAM pages and the rows that
-    // neighbours pull from stay few), one node per thread
+    // neighbours pull from stay few), one node per thread; a block of a
+    // narrow domain holds kThreads / width of its rows
     const int ridx = int(blockIdx.x);
-    const Tile t = a.rows[ridx];
+    const RowBlock t = a.rows[ridx];
     const DomainDev& D = a.dom[t.domain];
     const int nx = D.nx, ny = D.ny;
     const long long plane = D.plane;
@@ -224,11 +225,12 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     // above delta stores nothing, and the median pass reads its 64 columns as
     // zeros (the segment's partial records which waves stored).
     const bool every = (D.limiter & kLimEns) || D.median_mode != 0;
-    const Cols<T, BC> cl(t.x0 + int(threadIdx.x), nx, t.x0 + int(threadIdx.x) < t.x1);
+    const int lx = int(threadIdx.x) & (t.width - 1), ly = int(threadIdx.x) / t.width;
+    const int y = t.y0 + ly;
+    const Cols<T, BC> cl(t.x0 + lx, nx, t.x0 + lx < t.x1 && y < t.y1);
     AccT<A> acc;
     if (cl.ok) {
         {
-            const int y = t.y0;
             A g[Q];
             gather2d<BC>(src, plane, nx, ny, cl, y, g);
             const long long row = (long long)y * nx;
@@ -321,7 +323,9 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
             }
         }
     }
-    node_partial(acc, a.rowpart + (long long)ridx * kNStat, red);
+    // one partial per row of the block (row y, strip x0 / kThreads)
+    node_partial_rows(acc, a.rowpart + ((long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads) * kNStat,
+                      D.strips, t.width / kWave, t.y1 - t.y0, red);
 }
 
 // Second pass: median filter (Sec. 3.5; cavity stencils of Sec. 4.4) on the
@@ -477,7 +481,7 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             return;
         }
     }
-    AccT<A> acc;
+    AccT<A, double> acc;
     const int nx = D.nx, ny = D.ny;
     const int x = t.x0 + int(threadIdx.x);
     // rows y0-1 .. y1 are read; y1 <= ny, so one wrap keeps them in range
@@ -535,7 +539,7 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
                 if (D.limiter & kLimTopK) cand = cand || inf || mx > A(D.delta_trim);
             }
         }
-        active = __syncthreads_or(cand);
+        active = __syncthreads_or(cand || (a.flags & kFlagAllTiles));
         // staged only for a tile that has something to filter
         if (active && (D.limiter & kLimMedian) && sparse) {
             const int nr = rows + 2;
