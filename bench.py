@@ -338,30 +338,50 @@ def variants(torch, L, wl, stream, args):
     res["collision_4096_entropic"] = coll
 
     print("[bench] variant cavity ensemble (256 domains)", file=sys.stderr, flush=True)
-    batch = wl.cavity_batch(256)
+    res["cavity_ensemble_256"] = cavity_batch(torch, L, wl, stream, 200, one_by_one=True)
+    return res
+
+
+def batch_domains(L, wl, batch):
     doms = []
     for s in batch.specs:
         rho, u = wl.cavity_rest(s.n, s.n, rho0=1.0)
         doms.append(L.Domain(lattice=L.LBM_D2Q9, nx=s.n, ny=s.n, beta=s.beta, qe=L.LBM_QE_ENTROPIC,
                              limiter=L.LBM_LIM_MEDIAN, ds_form=L.LBM_DS_QUADRATIC, bc=L.LBM_BC_CAVITY,
                              delta_median=1e-3, rho0=1.0, lid_ux=0.1, rho_init=rho, u_init=u, probe=s.probe))
-    bsteps = 200
+    return doms
+
+
+def cavity_batch(torch, L, wl, stream, bsteps, one_by_one=False, kernel_steps=50, tile_x=0, tile_h=0):
+    """The seeded ensemble of 256 lid-driven cavities (N in {64, 100, 128,
+    192, 256}, Re in [2000, 7500], entropic f*, median filter delta = 1e-3),
+    FP32, all domains in one launch per kernel per step, shapes chosen by the
+    tuner; optionally against the same cavities run one context at a time."""
+    batch = wl.cavity_batch(256)
+    doms = batch_domains(L, wl, batch)
     with L.lbm_create(doms, L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=50,
-                                  probe_capacity=bsteps + 64)) as ctx:
+                                  probe_capacity=bsteps + 64, tile_x=tile_x, tile_h=tile_h)) as ctx:
+        shape = L.lbm_tile_config(ctx)
+        k1, k2, _ = kernel_times_warm(L, ctx, kernel_steps, 0.5)
         ms_batch = time_steps(torch, L, ctx, stream, bsteps, 20)
-    ms_single = 0.0
-    for d in doms:
-        with L.lbm_create([d], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=50,
-                                     probe_capacity=bsteps + 64)) as ctx:
-            ms_single += time_steps(torch, L, ctx, stream, bsteps, 20)
     sites = batch.sites
-    res["cavity_ensemble_256"] = {
-        "sites": sites, "steps": bsteps,
+    alg = 72 * sites
+    res = {
+        "sites": sites, "steps": bsteps, "tile": list(shape),
         "batched_mlups": round(sites * bsteps / (ms_batch * 1e3), 1),
-        "one_by_one_mlups": round(sites * bsteps / (ms_single * 1e3), 1),
-        "speedup": round(ms_single / ms_batch, 2),
-        "step_hbm_frac": round(72 * sites * bsteps / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "ms_per_step": round(ms_batch / bsteps, 5),
+        "collide_ms": round(k1, 5), "second_pass_ms": round(k2, 5),
+        "collide_hbm_frac": round(alg / (k1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_hbm_frac": round(alg * bsteps / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
+    if one_by_one:
+        ms_single = 0.0
+        for d in doms:
+            with L.lbm_create([d], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=50,
+                                         probe_capacity=bsteps + 64)) as ctx:
+                ms_single += time_steps(torch, L, ctx, stream, bsteps, 20)
+        res["one_by_one_mlups"] = round(sites * bsteps / (ms_single * 1e3), 1)
+        res["speedup"] = round(ms_single / ms_batch, 2)
     return res
 
 
@@ -424,12 +444,15 @@ def main():
                     help="seconds of graph steps before the per-kernel timing (clocks settle)")
     ap.add_argument("--no-active", action="store_true", help="skip the active-median companion run")
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity ensemble")
-    ap.add_argument("--tile-h", type=int, default=0, help="rows per median/reduction tile (1..64; 0: 64)")
+    ap.add_argument("--tile-h", type=int, default=0, help="rows per second-pass tile (16, 32, 64; 0: tuned)")
+    ap.add_argument("--tile-x", type=int, default=0,
+                    help="collision row blocks: 64 narrow, 256 full rows, 0 tuned (batch workload)")
     ap.add_argument("--delta-median", type=float, default=None,
                     help="median tolerance instead of 1e-4 (below the Delta S' of most nodes the filter acts)")
-    ap.add_argument("--workload", choices=("headline", "elbm", "smooth"), default="headline",
+    ap.add_argument("--workload", choices=("headline", "elbm", "smooth", "batch"), default="headline",
                     help="elbm: entropic f*, ELBM collisions, no limiter; smooth: the headline limiters plus "
-                         "the smooth ensemble factor (k = 1/2, delta = 0.01)")
+                         "the smooth ensemble factor (k = 1/2, delta = 0.01); batch: only the ensemble of 256 "
+                         "cavities (its own JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
@@ -462,6 +485,13 @@ def main():
         res = hopf.run(L, list(np_arange_inclusive(a, b, c)), n=args.hopf_n, time_units=args.hopf_units,
                        stream=stream.cuda_stream)
         print(json.dumps({"hopf": res}), flush=True)
+        return
+    if args.workload == "batch":
+        res = cavity_batch(torch, L, wl, stream, args.steps, kernel_steps=args.kernel_steps, tile_x=args.tile_x,
+                           tile_h=args.tile_h)
+        if args.calibrate_copy:
+            res["copy_calibration"] = copy_calibration(torch, stream)
+        print(json.dumps({"cavity_ensemble_256": res}), flush=True)
         return
     n = args.n
     dom = c2_domain(L, wl, n)

@@ -92,6 +92,47 @@ __device__ __forceinline__ double lane_shift(double v)
     return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
 }
 
+// Sum (MAX = false) or maximum (MAX = true) of v over the 64 lanes of a wave,
+// complete in lane 63: an inclusive scan inside each row of 16 lanes by DPP
+// row shifts 1, 2, 4, 8 (0x111..0x118; a lane whose source lies before its
+// row takes the identity), then the totals of rows 0 and 2 carried into
+// rows 1 and 3 (row_bcast:15, 0x142, row mask 0b1010) and the total of rows
+// 0-1 into rows 2-3 (row_bcast:31, 0x143, row mask 0b1100).  Six VALU
+// operations, each with its DPP source folded in; every lane of the wave
+// must be active.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ int dpp_id(int id, int v)
+{
+    return __builtin_amdgcn_update_dpp(id, v, CTRL, RMASK, 0xF, false);
+}
+template <bool MAX, int CTRL, int RMASK>
+__device__ __forceinline__ float scan_step(float v)
+{
+    constexpr int id = MAX ? int(0xff800000u) : 0;        // -inf or +0
+    const float o = __builtin_bit_cast(float, dpp_id<CTRL, RMASK>(id, __builtin_bit_cast(int, v)));
+    return MAX ? __builtin_fmaxf(v, o) : v + o;
+}
+template <bool MAX, int CTRL, int RMASK>
+__device__ __forceinline__ double scan_step(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    constexpr int id_hi = MAX ? int(0xfff00000u) : 0;      // -inf or +0
+    const int lo = dpp_id<CTRL, RMASK>(0, int(b & 0xffffffffll)), hi = dpp_id<CTRL, RMASK>(id_hi, int(b >> 32));
+    const double o = __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+    return MAX ? fmax(v, o) : v + o;
+}
+template <bool MAX, class S>
+__device__ __forceinline__ S wave_reduce(S v)
+{
+    v = scan_step<MAX, 0x111, 0xF>(v);
+    v = scan_step<MAX, 0x112, 0xF>(v);
+    v = scan_step<MAX, 0x114, 0xF>(v);
+    v = scan_step<MAX, 0x118, 0xF>(v);
+    v = scan_step<MAX, 0x142, 0xA>(v);
+    v = scan_step<MAX, 0x143, 0xC>(v);
+    return v;
+}
+
 // uniform base (SGPRs) + 32-bit byte offset (VGPR): lets the compiler use
 // the global_load/store "saddr + voffset" form instead of 64-bit lane addresses
 template <class T>
@@ -303,79 +344,37 @@ struct SiteScalars {
 // the sums' rounding lands alike at neighbouring nodes.  Both errors repeat
 // at every step of a slowly varying flow and add up (1e-5 of the velocity
 // after 1e3 steps of a lid-driven cavity), where an unbiased rounding of the
-// stored state alone stays near 1e-7.  So the FP32 path sums mass and
-// momentum with error-free transformations (TwoSum, Knuth) and takes the
-// momentum term with coefficients whose identity sum_i a_i v_i v_i = 1 holds
-// exactly in binary: a = fl(1/3) on the axes and (1 - 2 fl(1/3)) / 4
-// (exactly representable) on the diagonals of D2Q9, 1/2 in D1Q3.  The
-// entropic f* (square roots and reciprocals) is brought back to the node's
-// mass and momentum afterwards along the same coefficients.
+// stored state alone stays near 1e-7.  So the FP32 path forms mass and
+// momentum in FP64 (the nine FP32 terms and their sums and differences are
+// exact there unless their magnitudes span more than 2^25; the result is
+// rounded to FP32 once) and takes the momentum term with coefficients whose
+// identity sum_i a_i v_i v_i = 1 holds exactly in binary: a = fl(1/3) on the
+// axes and (1 - 2 fl(1/3)) / 4 (exactly representable) on the diagonals of
+// D2Q9, 1/2 in D1Q3.  The entropic f* (square roots and reciprocals) is
+// brought back to the node's mass and momentum afterwards along the same
+// coefficients.  FP64 adds issue at the rate of unpacked FP32 ones on this
+// part, so the nine conversions and sixteen adds cost less than the
+// error-free FP32 transformations that give the same result.
 
-// s + e = a + b exactly (round to nearest)
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
-{
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-// sum_i c_i g_i with c_i in {-1, 0, 1}, compensated (rounded once at the end)
-template <int Q, class C>
-__device__ __forceinline__ float comp_sum(const float (&g)[Q], C coef)
-{
-    float s = 0.0f, c = 0.0f;
-    bool first = true;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int k = coef(i);
-        if (k == 0) continue;
-        const float x = k > 0 ? g[i] : -g[i];
-        if (first) {
-            s = x;
-            first = false;
-        } else {
-            float e;
-            two_sum(s, x, s, e);
-            c += e;
-        }
-    }
-    return s + c;
-}
-
-// mass sum_i g_i and momentum sum_i v_i g_i, compensated.  D2Q9: sums and
-// differences of opposite populations first (the diagonal difference
-// g5 - g7 serves both components), then the short sums, each rounding error
-// kept and added back once.
+// mass sum_i g_i and momentum sum_i v_i g_i of FP32 terms, formed in FP64 and
+// rounded once.  D2Q9: sums and differences of opposite populations first
+// (the diagonal difference g5 - g7 serves both components).
 template <int LAT>
 __device__ __forceinline__ void comp_moments(const float (&g)[Lat<LAT>::Q], float& dr, float& jx, float& jy)
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q;
+    double d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = double(g[i]);
     if constexpr (LAT == kD2Q9) {
-        float p13, f13, p24, f24, p57, f57, p68, f68, s, e1, e2, e3, e4;
-        two_sum(g[1], g[3], p13, f13);
-        two_sum(g[2], g[4], p24, f24);
-        two_sum(g[5], g[7], p57, f57);
-        two_sum(g[6], g[8], p68, f68);
-        two_sum(p13, p24, s, e1);
-        two_sum(s, p57, s, e2);
-        two_sum(s, p68, s, e3);
-        two_sum(s, g[0], s, e4);
-        dr = s + (((f13 + f24) + (f57 + f68)) + ((e1 + e2) + (e3 + e4)));
-        float d13, e13, d57, e57, d86, e86, d24, e24, sx, ex1, ex2, sy, ey1, ey2;
-        two_sum(g[1], -g[3], d13, e13);
-        two_sum(g[5], -g[7], d57, e57);
-        two_sum(g[8], -g[6], d86, e86);
-        two_sum(g[2], -g[4], d24, e24);
-        two_sum(d13, d57, sx, ex1);
-        two_sum(sx, d86, sx, ex2);
-        two_sum(d24, d57, sy, ey1);
-        two_sum(sy, -d86, sy, ey2);
-        jx = sx + (((e13 + e57) + e86) + (ex1 + ex2));
-        jy = sy + (((e24 + e57) - e86) + (ey1 + ey2));
+        dr = float((((d[1] + d[3]) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]))) + d[0]);
+        const double d13 = d[1] - d[3], d24 = d[2] - d[4], d57 = d[5] - d[7], d86 = d[8] - d[6];
+        jx = float((d13 + d57) + d86);
+        jy = float((d24 + d57) - d86);
     } else {
-        dr = comp_sum<Q>(g, [](int) { return 1; });
-        jx = comp_sum<Q>(g, [](int i) { return L::vx(i); });
+        dr = float((d[1] + d[2]) + d[0]);
+        jx = float(d[2] - d[1]);
         jy = 0.0f;
     }
 }
@@ -860,23 +859,23 @@ __device__ inline void store_partial_rows(const AccT<S>& acc, double* out, doubl
 
 // Partials of a workgroup whose threads hold at most one node each, covering
 // `nrow` rows of `wpr` waves each (a row of 64 wpr columns): the sums (FP32
-// for reduced storage, FP64 for FP64 storage) by a fixed xor butterfly in
-// each wave, the 0/1 counts by ballots; then for each row its waves combined
-// in FP64 in order, written to out + r * stride (r < nrow).  kSAbove is a
-// bit mask there: bit w is set when wave w of the row holds a node above the
-// median tolerance (the median pass reads which waves stored Delta S').
+// for reduced storage, FP64 for FP64 storage) by a fixed DPP scan in each
+// wave (the limiter and entropy sums only in waves that hold one), the 0/1
+// counts by ballots; then for each row its waves combined in FP64 in order,
+// written to out + r * stride (r < nrow).  kSAbove is a bit mask there: bit
+// w is set when wave w of the row holds a node above the median tolerance
+// (the median pass reads which waves stored Delta S').
 template <class S>
 __device__ inline void node_partial_rows(const AccT<S>& acc, double* out, long long stride, int wpr, int nrow,
                                          double* lds /* [4 * kNStat] */)
 {
     S v[8] = {acc.mass, acc.jx, acc.jy, acc.dpre, acc.dpost, acc.maxd, acc.lim, acc.ent};
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const S o = __shfl_xor(v[k], off, 64);
-            v[k] = (k == kSMax) ? fmax(v[k], o) : v[k] + o;
+    for (int k = 0; k < 8; ++k) {
+        if (k == kSLim || k == kSEnt) {
+            if (!__ballot(v[k] != S(0))) continue;     // uniform: the wave holds none
         }
+        v[k] = k == kSMax ? wave_reduce<true>(v[k]) : wave_reduce<false>(v[k]);
     }
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -885,7 +884,7 @@ __device__ inline void node_partial_rows(const AccT<S>& acc, double* out, long l
                            double(__popcll(__ballot(acc.fluid != 0))),
                            __ballot(acc.above != 0) ? double(1 << (wave % wpr)) : 0.0,
                            double(__popcll(__ballot(acc.ens != 0))), double(__popcll(__ballot(acc.pos != 0)))};
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);
 #pragma unroll

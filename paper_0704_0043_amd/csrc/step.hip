@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     // above delta stores nothing, and the median pass reads its 64 columns as
     // zeros (the segment's partial records which waves stored).
     const bool every = (D.limiter & kLimEns) || D.median_mode != 0;
-    const int lx = int(threadIdx.x) & (t.width - 1), ly = int(threadIdx.x) / t.width;
+    // the block width is a power of two (64, 128 or 256)
+    const int lx = int(threadIdx.x) & (t.width - 1), ly = int(threadIdx.x) >> __builtin_ctz(unsigned(t.width));
     const int y = t.y0 + ly;
     const Cols<T, BC> cl(t.x0 + lx, nx, t.x0 + lx < t.x1 && y < t.y1);
     AccT<A> acc;
