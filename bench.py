@@ -17,7 +17,9 @@ kernel's average duration, measured with HIP events on its stream after half
 a second of graph steps has brought the clocks to their sustained level; this
 measurement runs before the warm-up and timed steps); the roofline of the
 whole step; the same step with the
-median filter moving a few percent of the nodes (delta_median = 1e-9); the
+median filter moving a few (delta_median = 1e-9) and some fifteen percent
+(delta_median = 0) of the nodes, with the two kernels and with the fused
+step; the
 max-norm error of a 1024 x 1024 replica against the FP64 CPU oracle; and that
 oracle timed on the host on the replica (its OpenMP build on the host's cores,
 and one thread).
@@ -217,19 +219,28 @@ def kernel_times_warm(L, ctx, steps=50, warm_seconds=0.5):
 
 def median_active(torch, L, wl, stream, n, steps=200):
     """The headline step with the median tolerance below the Delta S' of most
-    nodes (delta_median = 1e-9): the filter moves a few percent of the nodes
-    every step, so the second pass rescales stored states."""
-    dom = c2_domain(L, wl, n)
-    dom.delta_median = 1e-9
-    with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream)) as ctx:
-        ms = time_steps(torch, L, ctx, stream, steps, 16)
-        st = L.lbm_entropy_stats(ctx)
-        k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
+    nodes (delta_median = 1e-9, and 0): the filter moves a few percent (some
+    fifteen percent) of the nodes every step.  Timed with the two kernels as
+    tuned (the second pass rescales the moved nodes' stored states) and with
+    the fused step (tile_x = 248, collision and filter in one pass)."""
     sites = n * n
-    return {"delta_median": 1e-9, "mlups": round(sites * steps / (ms * 1e3), 1),
-            "ms_per_step": round(ms / steps, 5), "steps": steps, "collide_ms": round(k1, 5),
-            "median_ms": round(k2, 5), "filtered_fraction": round(st["n_filtered"] / sites, 4),
-            "step_hbm_frac": round(72 * sites / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out = {}
+    for dmed in (1e-9, 0.0):
+        res = {}
+        for name, tile_x in (("two_kernels", 0), ("fused", 248)):
+            dom = c2_domain(L, wl, n)
+            dom.delta_median = dmed
+            with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, tile_x=tile_x)) as ctx:
+                tile = L.lbm_tile_config(ctx)
+                ms = time_steps(torch, L, ctx, stream, steps, 16)
+                st = L.lbm_entropy_stats(ctx)
+                k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
+            res[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
+                         "tile": list(tile), "first_kernel_ms": round(k1, 5), "second_kernel_ms": round(k2, 5),
+                         "filtered_fraction": round(st["n_filtered"] / sites, 4),
+                         "step_hbm_frac": round(72 * sites / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[f"delta_median_{dmed:g}"] = dict(res, steps=steps)
+    return out
 
 
 def load_traffic():
@@ -565,8 +576,8 @@ def main():
         out["roofline"] = None
         out["note"] = "not the headline workload: kernel times only (no roofline, no traffic record)"
     if default and not args.no_active:
-        print("[bench] the same step with the median filter acting (delta_median = 1e-9)", file=sys.stderr,
-              flush=True)
+        print("[bench] the same step with the median filter acting (delta_median = 1e-9 and 0; two kernels "
+              "and the fused step)", file=sys.stderr, flush=True)
         out["median_active"] = median_active(torch, L, wl, stream, n)
     if args.calibrate_copy:
         out["copy_calibration"] = copy_calibration(torch, stream)

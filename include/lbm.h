@@ -182,10 +182,22 @@ typedef struct {
                                    64 = for a domain at most 128 wide, the narrowest of 64
                                    or 128 columns that spans its rows, with 4 or 2 rows per
                                    workgroup (wider domains keep 256); 0 = chosen by the
-                                   autotuner (see lbm_create) */
+                                   autotuner (see lbm_create); 248 = the fused step: one kernel
+                                   does the collision and the median filter (Sec. 3.5) over
+                                   tiles of 248 columns (four waves of 62 owned columns each;
+                                   LBGK domains with the median filter and no ensemble-dependent
+                                   limiter only, else LBM_EINVAL).  Its cost does not depend on
+                                   how many nodes the filter moves; the two kernels cost less
+                                   while few move and more when many do (each moved node's
+                                   stored state is read and written again).  The decisions are
+                                   the same; a moved node's state is formed once as
+                                   f* - phi c d (phi the smallest factor, eq. LimGenF), so its
+                                   populations agree with the two-kernel step to rounding */
     int32_t tile_y;             /* 0 (or 1) */
     int32_t tile_h;             /* rows per D2Q9 second-pass tile (1..64); 0 = chosen by the
-                                   autotuner among 16, 32 and 64 (64 without a second pass) */
+                                   autotuner among 16, 32 and 64 (64 without a second pass).
+                                   With tile_x = 248: rows per fused tile (1..128), 0 = chosen
+                                   among 8, 16, 32 and 64 */
     uint32_t flags;             /* LBM_RUN_* */
     int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
     int32_t graph_chunk;        /* longest captured step sequence, 1..4096, 0 = 64: lbm_create
@@ -226,8 +238,10 @@ LBM_API int lbm_workspace_bytes(const lbm_domain_desc* domains, int32_t n_domain
  * and the work tables, and captures the step graphs.  D2Q9 autotuner: unless
  * LBM_RUN_NO_TUNE or fixed by tile_x / tile_h, the candidate shapes (row
  * blocks of 256 columns or narrow ones; second-pass tiles of 16, 32 or 64
- * rows) are timed with HIP events on a few steps that all read the initial
- * state (which they leave unchanged), and the fastest is kept; the choice is
+ * rows; with tile_x = 248 the fused tile heights) are timed with HIP events
+ * on a few steps that all read the initial state (which they leave
+ * unchanged), each scored by a step as it stands plus one whose second pass
+ * walks every tile, and the fastest is kept; the choice is
  * cached for the process under the descriptors, so later contexts of the
  * same problem reuse it.  The shapes do not change the fields or E(Delta S');
  * the FP64 sums the second pass adds to (limiter production) can differ in
@@ -269,7 +283,8 @@ LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max
 
 /* Shape in use.  D2Q9: columns of the first domain's collision row blocks
  * (256, or 64 / 128 for a narrow domain), their rows per workgroup, and the
- * rows of a second-pass tile.  D1Q3: 254, 1, 1. */
+ * rows of a second-pass tile; the fused step: 248, 1 and the rows of a fused
+ * tile.  D1Q3: 254, 1, 1. */
 LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
 
 /* sync; profiling aid outside the method.  Advances the state by n_steps

@@ -436,7 +436,7 @@ hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s)
 
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s)
 {
-    if (a.nrows > 0) {
+    if (a.nrows > 0 && !a.fused) {
         hipLaunchKernelGGL(k_tile_rows, dim3(a.ngroups), dim3(kThreads), 0, s, a, parity_done);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -28,6 +28,8 @@ thread_local std::string g_err;
 
 constexpr size_t kAlign = 256;
 constexpr int kMinTuneH = 16;   // smallest median-tile height the tuner tries
+constexpr int kMinFusedH = 8;   // smallest fused-tile height the tuner tries
+constexpr int kMaxFusedH = 128; // tallest fused tile
 
 // D2Q9 tiles: kThreads consecutive columns
 int strips_of(int nx) { return (nx + kThreads - 1) / kThreads; }
@@ -95,6 +97,8 @@ struct lbm_ctx {
     int ntiles = 0;
     bool median_pass = false;   // D2Q9 with the median filter in some domain
     bool ens_pass = false;      // an ensemble-dependent limiter in some domain
+    bool fuse_ok = false;       // the fused step applies (D2Q9 LBGK, median filter, no ensemble limiter)
+    bool fused = false;         // the fused step runs (tiles are fused tiles)
     bool budget = false;        // the budget threshold in some domain
     bool elbm = false;          // ELBM collisions (all domains)
     long long steps_done = 0, finalized_for = -1;
@@ -146,10 +150,11 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
     if (!doms || nd < 1 || !run) return fail(nullptr, LBM_EINVAL, "domains/run must be non-NULL, n_domains >= 1");
     if (run->struct_size < sizeof(lbm_run_desc)) return fail(nullptr, LBM_EINVAL, "lbm_run_desc.struct_size too small");
     if (run->storage < LBM_F64 || run->storage > LBM_BF16_SHIFT) return fail(nullptr, LBM_EINVAL, "bad storage");
-    if (run->tile_x != 0 && run->tile_x != kWave && run->tile_x != kThreads)
-        return fail(nullptr, LBM_EINVAL, "tile_x must be 0 (tuned), 64 (narrow row blocks) or 256");
+    if (run->tile_x != 0 && run->tile_x != kWave && run->tile_x != kThreads && run->tile_x != kFusedWidth)
+        return fail(nullptr, LBM_EINVAL, "tile_x must be 0 (tuned), 64 (narrow row blocks), 256 or 248 (fused step)");
     if (run->tile_y != 0 && run->tile_y != 1) return fail(nullptr, LBM_EINVAL, "tile_y must be 0 or 1");
-    if (run->tile_h < 0 || run->tile_h > kMaxTileH) return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 64]");
+    if (run->tile_h < 0 || run->tile_h > (run->tile_x == kFusedWidth ? kMaxFusedH : kMaxTileH))
+        return fail(nullptr, LBM_EINVAL, "tile_h out of range [0, 64] (fused step: [0, 128])");
     if (run->graph_chunk < 0 || run->graph_chunk > 4096)
         return fail(nullptr, LBM_EINVAL, "graph_chunk out of range [0, 4096]");
     if (run->probe_capacity < 0) return fail(nullptr, LBM_EINVAL, "probe_capacity < 0");
@@ -306,7 +311,9 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         off = plan_extras(h, storage, off);
         // the tile table is sized for the smallest height the tuner may pick
         const int min_h = run->tile_h > 0 ? run->tile_h : kMinTuneH;
-        const int tiles = tiles_of(h.d.lattice, h.d.nx, h.d.ny, min_h);
+        int tiles = tiles_of(h.d.lattice, h.d.nx, h.d.ny, min_h);
+        if (h.d.lattice == LBM_D2Q9 && run->tile_x == kFusedWidth)
+            tiles = std::max(tiles, fused_tiles_of(h.d.nx, h.d.ny, run->tile_h > 0 ? run->tile_h : kMinFusedH));
         L.max_tiles += tiles;
         L.ngroups += tiles_of(h.d.lattice, h.d.nx, h.d.ny, kMaxTileH);
         if (h.d.lattice == LBM_D2Q9) L.nrows += strips_of(h.d.nx) * h.d.ny;
@@ -336,17 +343,18 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
 // the rows).  The kernels map workgroups to runs of this order XCD by XCD
 // (xcd_spatial), so vertically adjacent tiles, which share halo rows, run
 // on the same L2, and per-domain partial ranges stay contiguous.
-std::vector<Tile> build_tiles(lbm_ctx* ctx, int th)
+std::vector<Tile> build_tiles(lbm_ctx* ctx, int th, bool fused)
 {
     std::vector<Tile> spatial;
     for (size_t k = 0; k < ctx->dom.size(); ++k) {
         DomainHost& h = ctx->dom[k];
         h.tile_first = int(spatial.size());
         const int nx = h.d.nx, ny = h.d.ny;
-        const int count = tiles_of(ctx->lattice, nx, ny, th);
+        const int count = fused ? fused_tiles_of(nx, ny, th) : tiles_of(ctx->lattice, nx, ny, th);
         for (int i = 0; i < count; ++i)
-            spatial.push_back(ctx->lattice == LBM_D2Q9 ? tile_entry2d(int(k), nx, ny, th, i)
-                                                       : tile_entry1d(int(k), nx, i));
+            spatial.push_back(fused ? fused_tile_entry(int(k), nx, ny, th, i)
+                                    : (ctx->lattice == LBM_D2Q9 ? tile_entry2d(int(k), nx, ny, th, i)
+                                                                : tile_entry1d(int(k), nx, i)));
         h.tile_count = count;
     }
     return spatial;
@@ -461,9 +469,10 @@ int upload_domains(lbm_ctx* ctx)
     return LBM_OK;
 }
 
-int set_tiles(lbm_ctx* ctx, int th)
+int set_tiles(lbm_ctx* ctx, int th, bool fused = false)
 {
-    ctx->tiles_host = build_tiles(ctx, th);
+    ctx->tiles_host = build_tiles(ctx, th, fused);
+    ctx->fused = fused;
     if (int(ctx->tiles_host.size()) > ctx->lay.max_tiles) return fail(ctx, LBM_EINVAL, "tile table overflow");
     ctx->ntiles = int(ctx->tiles_host.size());
     ctx->th = th;
@@ -485,6 +494,7 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     a.median_pass = (ctx->median_pass || ctx->ens_pass) ? 1 : 0;
     a.ens_pass = ctx->ens_pass ? 1 : 0;
     a.budget = ctx->budget ? 1 : 0;
+    a.fused = ctx->fused ? 1 : 0;
     a.rows = ctx->d_rows();
     a.nrows = int(ctx->rows_host.size());
     a.groups = ctx->d_groups();
@@ -501,7 +511,7 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
 // The kernels one step launches (what a context or a static call runs).
 struct StepKind {
     int storage, lattice, qe, ds, bc;
-    bool elbm, median_pass, ens_pass, budget;
+    bool elbm, median_pass, ens_pass, budget, fused = false;
 };
 
 // One step of every domain of `a`.  With `ev` (three events) the launches
@@ -510,6 +520,13 @@ hipError_t launch_step(const StepKind& k, const StepArgs& a, hipStream_t s, hipE
 {
     hipError_t e = hipSuccess;
     if (ev) e = hipEventRecord(ev[0], s);
+    if (k.fused) {
+        // one kernel: collision and median filter together
+        if (e == hipSuccess) e = launch_step2d(k.storage, k.qe, k.ds, k.bc, a, 3, s);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
+        return e;
+    }
     if (e == hipSuccess) {
         if (k.lattice == LBM_D2Q9)
             e = launch_step2d(k.storage, k.qe, k.ds, k.bc, a, k.elbm ? 2 : 0, s);
@@ -533,7 +550,7 @@ hipError_t launch_step(const StepKind& k, const StepArgs& a, hipStream_t s, hipE
 StepKind step_kind(const lbm_ctx* ctx)
 {
     return StepKind{ctx->storage, ctx->lattice, ctx->qe, ctx->ds, ctx->bc, ctx->elbm, ctx->median_pass,
-                    ctx->ens_pass, ctx->budget};
+                    ctx->ens_pass, ctx->budget, ctx->fused};
 }
 
 int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr, unsigned extra_flags = 0)
@@ -566,22 +583,41 @@ void drop_graphs(lbm_ctx* ctx)
 }
 
 // ---- autotuner ---------------------------------------------------------------
-// Two shape choices change the speed of a D2Q9 step and nothing it computes:
-// the row blocks of the collision kernel (256 columns per row, or several rows
-// of a narrow domain per workgroup) and the height of the tiles the second pass
-// walks (the stats partials are grouped by fixed 64-row groups, so E(Delta S')
-// and every field come out the same for any height; only the FP64 sums that
-// the second pass adds to may differ in the last bits).  lbm_create times the
-// candidate shapes on the live state with HIP events and keeps the fastest; a
-// process-wide cache keyed by the descriptors gives the same choice to every
-// later context of the same problem.
+// Three shape choices change the speed of a D2Q9 step: the row blocks of the
+// collision kernel (256 columns per row, or several rows of a narrow domain
+// per workgroup), the height of the tiles the second pass walks, and, for
+// domains with the median filter and no ensemble-dependent limiter, the fused
+// step (collision and median filter in one pass over tiles of kFusedWidth
+// columns) in place of the two kernels, taken when the run asks for it
+// (tile_x = kFusedWidth; the tuner then picks its tile height).  The fused
+// step costs the same whatever the filter does; the two kernels cost less
+// while few nodes move and more when many do (each moved node's stored state
+// is read and written again), which the steps timed at creation, from a
+// state where nothing has moved yet, cannot show.  Row blocks and tile heights change
+// nothing the step computes (the stats partials are grouped by fixed 64-row
+// groups, so E(Delta S') and every field come out the same; only the FP64
+// sums that the second pass adds to may differ in the last bits).  The fused
+// step forms a moved node's state f* - phi c d once, with phi the smallest
+// factor, where the two kernels rescale the stored trimmed state: the masks
+// and every decision are the same, a moved node's populations agree to
+// rounding.  lbm_create times the candidate shapes on the live state with HIP
+// events and keeps the fastest; a process-wide cache keyed by the descriptors
+// gives the same choice to every later context of the same problem.
+
+struct Shape {
+    int narrow, th;
+    bool fused;
+};
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;   // key -> (narrow, tile height)
+std::map<std::string, Shape> g_tune_cache;   // key -> chosen shape
 
-std::string tune_key(const lbm_ctx* ctx)
+// the problem and the shapes the run allows (a run that fixes tile_x or
+// tile_h has its own entry)
+std::string tune_key(const lbm_ctx* ctx, const lbm_run_desc* run)
 {
-    std::string k = std::to_string(ctx->device) + "/" + std::to_string(ctx->storage) + "/" + std::to_string(ctx->qe) +
+    std::string k = std::to_string(run->tile_x) + "/" + std::to_string(run->tile_h) + "/" +
+                    std::to_string(ctx->device) + "/" + std::to_string(ctx->storage) + "/" + std::to_string(ctx->qe) +
                     "/" + std::to_string(ctx->ds) + "/" + std::to_string(ctx->bc) + "/" + std::to_string(ctx->elbm) +
                     "/" + std::to_string(ctx->flags & (LBM_RUN_RECORD | LBM_RUN_ENTROPY));
     for (const auto& h : ctx->dom)
@@ -591,11 +627,11 @@ std::string tune_key(const lbm_ctx* ctx)
     return k;
 }
 
-int apply_shape(lbm_ctx* ctx, int narrow, int th)
+int apply_shape(lbm_ctx* ctx, const Shape& sh)
 {
-    build_rows(ctx, narrow);
+    build_rows(ctx, sh.narrow);
     int rc = upload_rows(ctx);
-    return rc ? rc : set_tiles(ctx, th);
+    return rc ? rc : set_tiles(ctx, sh.th, sh.fused);
 }
 
 // average milliseconds of `n` steps that all read buffer 0 (the initial state
@@ -626,39 +662,53 @@ int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
     if (run->tile_x == kThreads || !any_narrow) widths = {0};
     else if (run->tile_x == kWave) widths = {1};
     else widths = {1, 0};
+    const bool second = ctx->median_pass || ctx->ens_pass;
     std::vector<int> heights;
     if (run->tile_h > 0) heights = {run->tile_h};
-    else if (ctx->median_pass || ctx->ens_pass) heights = {16, 32, 64};
+    else if (second) heights = {16, 32, 64};
     else heights = {kMaxTileH};
+    std::vector<Shape> cand;
+    if (run->tile_x != kFusedWidth)
+        for (int w : widths)
+            for (int th : heights) cand.push_back({w, th, false});
+    // the fused step only when asked for: at creation no node has moved yet,
+    // and the tuner cannot see how much of the flow the filter will move
+    if (ctx->fuse_ok && run->tile_x == kFusedWidth) {
+        const std::vector<int> fh = run->tile_h > 0 ? std::vector<int>{run->tile_h}
+                                                    : std::vector<int>{kMinFusedH, 16, 32, 64};
+        for (int th : fh) cand.push_back({widths[0], th, true});
+    }
     ctx->tuned = 0;
-    if ((ctx->flags & LBM_RUN_NO_TUNE) || widths.size() * heights.size() == 1)
-        return apply_shape(ctx, widths[0], heights.back());
-    const std::string key = tune_key(ctx);
+    if (cand.size() == 1) return apply_shape(ctx, cand[0]);
+    if (ctx->flags & LBM_RUN_NO_TUNE) {
+        // narrow row blocks where a domain allows them, tile_h or 64 rows
+        // for the second pass; the fused step only when asked for
+        if (run->tile_x == kFusedWidth) return apply_shape(ctx, {widths[0], run->tile_h > 0 ? run->tile_h : 64, true});
+        return apply_shape(ctx, {widths[0], heights.back(), false});
+    }
+    const std::string key = tune_key(ctx, run);
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             ctx->tuned = 1;
-            return apply_shape(ctx, it->second.first, it->second.second);
+            return apply_shape(ctx, it->second);
         }
     }
-    // Warm the part up on the default shape, then time every candidate in two
-    // rounds (the second in reverse order) and keep each one's best.  How
+    // Warm the part up on the first candidate, then time every candidate in
+    // two rounds (the second in reverse order) and keep each one's best.  How
     // much of the second pass has work depends on the flow (at the start
     // often no tile has a candidate); a candidate is scored by the sum of a
-    // step as it stands and a step whose second pass walks every tile.
-    const bool second = ctx->median_pass || ctx->ens_pass;
-    int rc = apply_shape(ctx, widths[0], heights.back());
+    // step as it stands and a step whose second pass walks every tile (the
+    // fused step does its median work on every node either way).
+    int rc = apply_shape(ctx, cand[0]);
     double ms = 0;
     if (!rc) rc = time_shape(ctx, 8, ms);
-    std::vector<std::pair<int, int>> cand;
-    for (int w : widths)
-        for (int th : heights) cand.push_back({w, th});
     std::vector<double> best(cand.size(), 1e30), best_all(cand.size(), second ? 1e30 : 0.0);
     for (int round = 0; round < 2 && !rc; ++round)
         for (size_t j = 0; j < cand.size() && !rc; ++j) {
             const size_t c = round ? cand.size() - 1 - j : j;
-            rc = apply_shape(ctx, cand[c].first, cand[c].second);
+            rc = apply_shape(ctx, cand[c]);
             if (!rc) rc = time_shape(ctx, 3, ms);
             if (!rc) best[c] = std::min(best[c], ms);
             if (!rc && second) rc = time_shape(ctx, 3, ms, kFlagAllTiles);
@@ -673,7 +723,7 @@ int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
         g_tune_cache[key] = cand[pick];
     }
     ctx->tuned = 1;
-    return apply_shape(ctx, cand[pick].first, cand[pick].second);
+    return apply_shape(ctx, cand[pick]);
 }
 
 // Capture `len` steps starting at `parity` into one executable graph.
@@ -894,11 +944,16 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         ctx->ens_pass = ctx->ens_pass || deferred(h.d);
         ctx->budget = ctx->budget || (h.d.limiter & kLimEnsBudget) || is_topk(h.d);
     }
+    ctx->fuse_ok = ctx->lattice == LBM_D2Q9 && !ctx->elbm && ctx->median_pass && !ctx->ens_pass;
 
     auto bail = [&](int code) {
         release(ctx);
         return code;
     };
+    if (run->tile_x == kFusedWidth && !ctx->fuse_ok)
+        return bail(fail(nullptr, LBM_EINVAL,
+                         "tile_x = 248 (fused step) needs D2Q9 LBGK domains with the median filter and no "
+                         "ensemble-dependent limiter"));
     hipError_t e = hipSetDevice(run->device);
     if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e)));
     if (run->stream) {
@@ -968,7 +1023,7 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("groups: ") + hipGetErrorString(e)));
     // the tuner runs steps: the step counters must hold valid indices first
     rc = reset_counters(ctx);
-    if (!rc) rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run) : apply_shape(ctx, 0, 1);
+    if (!rc) rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run) : apply_shape(ctx, Shape{0, 1, false});
     if (rc) {
         g_err = ctx->err;
         return bail(rc);
@@ -1138,9 +1193,10 @@ int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_
     // D2Q9: columns of the first domain's row blocks (256, or 64 / 128 for a
     // narrow domain), their rows per workgroup, and the second pass's tile
     // height; D1Q3: sites per workgroup, 1, 1
-    const int width = d2 ? seg_width(ctx->dom[0].d.nx, ctx->narrow) : k1DWidth;
+    // height; the fused step reports kFusedWidth, 1 and its tile height
+    const int width = ctx->fused ? kFusedWidth : (d2 ? seg_width(ctx->dom[0].d.nx, ctx->narrow) : k1DWidth);
     if (tile_x) *tile_x = width;
-    if (tile_y) *tile_y = d2 ? kThreads / width : 1;
+    if (tile_y) *tile_y = (d2 && !ctx->fused) ? kThreads / width : 1;
     if (tile_h) *tile_h = d2 ? ctx->th : 1;
     return LBM_OK;
 }
@@ -1176,7 +1232,7 @@ int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     ms[0] = t[0] / double(n_steps);
-    ms[1] = (ctx->median_pass || ctx->ens_pass) ? t[1] / double(n_steps) : 0.0;
+    ms[1] = ((ctx->median_pass || ctx->ens_pass) && !ctx->fused) ? t[1] / double(n_steps) : 0.0;
     return LBM_OK;
 }
 

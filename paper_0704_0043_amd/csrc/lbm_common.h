@@ -178,6 +178,26 @@ __host__ __device__ inline int tiles_of(int lattice, int nx, int ny, int th)
     return lattice == kD2Q9 ? ((nx + kThreads - 1) / kThreads) * ((ny + th - 1) / th) : (nx + k1DWidth - 1) / k1DWidth;
 }
 
+// The fused D2Q9 step (collision and median filter in one pass): each wave
+// computes 64 adjacent columns and keeps the 62 inner ones (the two outer
+// lanes supply the stencil's neighbours), so a workgroup of four waves owns
+// kFusedWidth columns of a tile of th rows (plus one halo row above and
+// below, computed for their Delta S' only).
+constexpr int kFusedCols = kWave - 2;
+constexpr int kFusedWidth = (kThreads / kWave) * kFusedCols;
+__host__ __device__ inline int fused_tiles_of(int nx, int ny, int th)
+{
+    return ((nx + kFusedWidth - 1) / kFusedWidth) * ((ny + th - 1) / th);
+}
+__host__ __device__ inline Tile fused_tile_entry(int domain, int nx, int ny, int th, int i)
+{
+    const int strips = (nx + kFusedWidth - 1) / kFusedWidth;
+    const int chunks = (ny + th - 1) / th;
+    const int r = i / strips, x0 = (i - r * strips) * kFusedWidth;
+    return Tile{domain, x0, x0 + kFusedWidth < nx ? x0 + kFusedWidth : nx, r * th, r * th + th < ny ? r * th + th : ny,
+                r, chunks, 1};
+}
+
 struct StepArgs {
     const DomainDev* dom;
     const Tile* tiles;      // spatial order (domain, row chunk, column strip)
@@ -193,6 +213,8 @@ struct StepArgs {
     int ngroups;
     int pstride;            // slots per set in `partials` (>= ntiles, ngroups)
     int median_pass;        // 1 if a second pass (median and/or ensemble limiters) writes set 1
+    int fused = 0;          // 1: the fused step kernel runs alone over `tiles` (fused tiles)
+                            // and writes every partial to set 1
     int ens_pass;           // 1 if some domain has an ensemble-dependent limiter
     int budget;             // 1 if some domain has the budget threshold
     const RowBlock* rows;   // D2Q9 row blocks in row-major order, one per collision workgroup
@@ -213,7 +235,8 @@ hipError_t launch_static_stats(const DomainDev* dom, double shift_mass, double* 
 
 // Launchers (one per storage type / lattice), defined in the .hip files.
 // kernel 0: collision kernel (LBGK); kernel 2: the same with the ELBM collision;
-// kernel 1: the second pass (median filter, ensemble factors; after kernel 0 or 2)
+// kernel 1: the second pass (median filter, ensemble factors; after kernel 0 or 2);
+// kernel 3: the fused step (LBGK, trimming, positivity and median filter)
 hipError_t launch_step2d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);
 // kernel 0: D1Q3 step (LBGK); kernel 2: the same with ELBM; kernel 1: D1Q3 ensemble pass
 hipError_t launch_step1d(int storage, int qe, int ds, int bc, const StepArgs& a, int kernel, hipStream_t s);

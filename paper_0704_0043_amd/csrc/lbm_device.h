@@ -1027,7 +1027,8 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
     // set 0: collision partials per group (D2Q9: summed from the rows on
     // demand); set 1: the second pass per tile, when it ran
     const double* part = a.partials + (long long)parity * 2 * a.pstride * kNStat;
-    const int nsets = a.median_pass ? 2 : 1;
+    // the fused step writes set 1 only
+    const int set0 = a.fused ? 1 : 0, nsets = (a.median_pass || a.fused) ? 2 : 1;
     // domains with few slots: one thread each, slots summed in order
     for (int d = tid; d < a.ndomains; d += nthr) {
         const DomainDev& D = a.dom[d];
@@ -1037,7 +1038,7 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
         double v[kNStat];
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) v[k] = 0;
-        for (int set = 0; set < nsets; ++set) {
+        for (int set = set0; set < nsets; ++set) {
             const int first = set ? D.tile_first : D.group_first, count = set ? D.tile_count : D.group_count;
             for (int t = 0; t < count; ++t) {
                 const double* p = part + ((long long)set * a.pstride + first + t) * kNStat;
@@ -1056,7 +1057,7 @@ __device__ inline void reduce_partials(const StepArgs& a, int parity, long long 
         double v[kNStat];
 #pragma unroll
         for (int k = 0; k < kNStat; ++k) v[k] = 0;
-        for (int set = 0; set < nsets; ++set) {
+        for (int set = set0; set < nsets; ++set) {
             const int first = set ? D.tile_first : D.group_first, count = set ? D.tile_count : D.group_count;
             for (int t = tid; t < count; t += nthr) {
                 const double* p = part + ((long long)set * a.pstride + first + t) * kNStat;

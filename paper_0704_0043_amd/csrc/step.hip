@@ -87,8 +87,8 @@ __device__ inline double* partial_slot(const StepArgs& a, int set, int tile)
 }
 
 // trimming factor of one node (it depends on the node alone, Sec. 3.2/3.4)
-template <class A>
-__device__ __forceinline__ A trim_phi(const DomainDev& D, A dpost, unsigned& mask)
+template <class A, class DD>
+__device__ __forceinline__ A trim_phi(const DD& D, A dpost, unsigned& mask)
 {
     A phi = A(1);
     if ((D.limiter & kLimTrim) && dpost > A(D.delta_trim)) {
@@ -345,8 +345,8 @@ constexpr int kPipe = 4;     // moved rows whose stored states are loaded togeth
 
 // the filter's threshold and decision for a node with Delta S' = dc whose
 // stencil median is med (FLOOR or GATE reading of the tolerance delta)
-template <class A>
-__device__ __forceinline__ bool median_decide(const DomainDev& D, A dc, A med, A& thr)
+template <class A, class DD>
+__device__ __forceinline__ bool median_decide(const DD& D, A dc, A med, A& thr)
 {
     const A dmed = A(D.delta_median);
     if (D.median_mode) {
@@ -359,8 +359,8 @@ __device__ __forceinline__ bool median_decide(const DomainDev& D, A dc, A med, A
 
 // median threshold of a fluid node from its window (rows b, c, n = y-1, y, y+1;
 // columns l, m, r = x-1, x, x+1); returns whether the filter hits the node
-template <int BC, class A>
-__device__ __forceinline__ bool median_hit(const DomainDev& D, int x, int y, int nx, int ny, const A (&b)[3],
+template <int BC, class A, class DD>
+__device__ __forceinline__ bool median_hit(const DD& D, int x, int y, int nx, int ny, const A (&b)[3],
                                            const A (&c)[3], const A (&n)[3], A& thr)
 {
     A med;
@@ -734,6 +734,285 @@ __global__ void __launch_bounds__(kThreads) k_median_ens2d(StepArgs a)
     second_pass2d<T, QE, DS, BC, true>(a);
 }
 
+// The domain fields the fused step reads in its row loop.
+struct FusedDom {
+    int nx, ny, limiter, trim_mode, median_mode, homothety, diffusive, probe_x, probe_y, probe_cap;
+    double delta_trim, delta_median, lid_ux, rho0;
+    float* probe;
+    unsigned char* mask;
+    double* dS;
+};
+
+// the exact homothety as a real call (its root solve would otherwise be
+// inlined twice into the fused kernel's row loop)
+template <class A>
+__device__ __attribute__((noinline)) A exact_homothety_call(const SiteState<kD2Q9, A>& o, A shift, A t, A dpost)
+{
+    return exact_homothety<kD2Q9>(o, shift, t, dpost);
+}
+
+// Fused D2Q9 step: collision, trimming, positivity and the median filter of
+// Sec. 3.5 (cavity stencils of Sec. 4.4) in one pass, for domains without
+// ensemble-dependent limiters.  Each wave walks down 64 adjacent columns of a
+// tile, lane l on column xw - 1 + l: lanes 1..62 own the wave's columns, lanes
+// 0 and 63 compute the neighbours that the owned columns' stencils read (their
+// Delta S' reaches the owned lanes by DPP lane shifts), and the rows above
+// and below the tile are computed for their Delta S' only.  A row is decided
+// one row later, when the Delta S' of the row below it is known; meanwhile
+// it keeps f* and the nonequilibrium part, so that its final state
+// f* - phi c d is formed once, phi the smallest of the trimming, positivity
+// and median factors (as in eq. (LimGenF) with the factors of Sec. 3).  The
+// gathers of the next row are issued before the current row is computed.  No
+// Delta S' plane is written; one FP64 partial per tile goes to set 1.
+template <class T, int QE, int DS, int BC>
+__global__ void __launch_bounds__(kThreads) k_fused2d(StepArgs a)
+{
+    using A = typename Store<T>::A;
+    using L = Lat<kD2Q9>;
+    constexpr int Q = 9;
+    __shared__ double red[4 * kNStat];
+    // the pending row's f* and nonequilibrium part, one column per thread
+    // (each thread reads back only its own slots)
+    __shared__ A pend[2 * Q][kThreads];
+    const int tidx = tile_of_block(a, 0);
+    const Tile t = a.tiles[tidx];
+    // the fields the walk reads, copied once: held in scalar registers (read
+    // through the table they would be reloaded, each time with a wait for
+    // every load in flight, after each store)
+    const DomainDev& Dt = a.dom[t.domain];
+    const FusedDom D{Dt.nx, Dt.ny, Dt.limiter, Dt.trim_mode, Dt.median_mode, Dt.homothety, Dt.diffusive,
+                     Dt.probe_x, Dt.probe_y, Dt.probe_cap, Dt.delta_trim, Dt.delta_median, Dt.lid_ux, Dt.rho0,
+                     Dt.probe, Dt.mask, Dt.dS};
+    const int nx = D.nx, ny = D.ny;
+    const long long plane = Dt.plane;
+    const gptr<const T> src = to_global<T>(static_cast<const void*>(Dt.buf[a.parity]));
+    const gptr<T> dst = to_global<T>(Dt.buf[1 - a.parity]);
+    const A shift = A(Dt.shift), c = A(Dt.c);
+    const bool record = a.flags & kFlagRecord;
+    const bool want_ent = a.flags & kFlagEntropy;
+    const bool median = D.limiter & kLimMedian;
+    const long long step = a.counter[a.parity];
+    // the index of the next step, read by the next launch (which reads buffer 1 - parity)
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counter[1 - a.parity] = step + 1;
+
+    const int lane = int(threadIdx.x) & (kWave - 1);
+    const int xw = t.x0 + (int(threadIdx.x) >> 6) * kFusedCols;   // the wave's first owned column
+    const int xw1 = xw + kFusedCols < t.x1 ? xw + kFusedCols : t.x1;
+    // per-thread sums over the rows it owns: moments and limiter production
+    // in FP64, the rest in the arithmetic type
+    AccT<A, double> acc;
+    double am = 0.0, ax = 0.0, ay = 0.0;
+    if (xw < t.x1) {   // uniform per wave
+        // the lane's column; lanes past the right neighbour of the last owned
+        // column repeat it (their values are never used)
+        const int x = xw - 1 + lane;
+        const int xe = x < xw1 ? x : xw1;
+        const bool owned = lane >= 1 && x < xw1;
+        bool in_x = true;
+        int xc = xe;
+        if constexpr (BC == kPeriodic) {
+            xc = xe < 0 ? xe + nx : (xe >= nx ? xe - nx : xe);
+        } else {
+            in_x = xe >= 0 && xe < nx;
+            xc = xe < 0 ? 0 : (xe >= nx ? nx - 1 : xe);
+        }
+        const Cols<T, BC> cl(xc, nx, true);
+        // rows y0 - 1 .. y1; off a cavity they are no nodes (clamped loads)
+        auto row_of = [&](int y) -> int {
+            if constexpr (BC == kPeriodic) return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+            else return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        };
+        // Delta S' window of the node's stencil: rows y - 2 (b), y - 1 (m)
+        // and y (n) relative to the row being computed; [0] left, [1] own,
+        // [2] right column
+        A wb[3] = {A(0), A(0), A(0)}, wm[3] = {A(0), A(0), A(0)};
+        // the pending row (the one above the row being computed): f* and d
+        // in LDS, the rest here
+        const int tid = int(threadIdx.x);
+        A p_dpost = A(0), p_phi = A(1);
+        unsigned p_mask = 0;
+        bool p_fluid = false;
+        // one row: collision of row y from its gathered populations g, then the
+        // decision and store of row y - 1
+        auto do_row = [&](int y, const A (&g)[Q]) {
+            const int yr = row_of(y);
+            const bool in_dom = in_x && (BC == kPeriodic || (y >= 0 && y < ny));
+            const int cls = in_dom ? node_class<BC>(xc, yr, nx, ny) : int(kNodeNone);
+            const bool own = owned && y >= t.y0 && y < t.y1;
+            const long long row = (long long)yr * nx;
+            const unsigned node = unsigned(row) + unsigned(xc);
+            SiteState<kD2Q9, A> S;
+            SiteScalars sc;
+            A dcur = A(0);
+            unsigned mask = 0;
+            A phi = A(1);
+            if (cls == kNodeFluid) {
+                collide_site<kD2Q9, QE, DS, false>(g, shift, c, S, sc, true);
+                dcur = S.dpost;
+                if (own) {
+                    am += sc.dr;
+                    ax += sc.jx;
+                    ay += sc.jy;
+                    if (!(isfinite(sc.dr) && isfinite(sc.jx) && isfinite(sc.jy))) ++acc.nonfin;
+                    acc.fluid_site(sc, S.dpost);
+                    if (want_ent) {
+                        const double e = entropy_site<kD2Q9>(g, shift);
+                        if (isfinite(e)) acc.ent += A(e);
+                    }
+                    if (xc == D.probe_x && yr == D.probe_y) {
+                        const gptr<float> pr = to_global<float>(D.probe) + 2 * (step % D.probe_cap);
+                        pr[0] = sc.ux;
+                        pr[1] = sc.uy;
+                    }
+                    phi = trim_phi(D, S.dpost, mask);
+                    if constexpr (DS == kExact) {
+                        if (D.homothety && (mask & kMaskTrim) && !D.trim_mode && isfinite(S.dpost))
+                            phi = exact_homothety_call(S, shift, A(D.delta_trim), S.dpost);
+                    }
+                    if (D.limiter & kLimPos) {
+                        const A pp = positivity_phi<kD2Q9>(S, shift);
+                        if (pp < A(1)) {
+                            mask |= kMaskPos;
+                            ++acc.pos;
+                            phi = fmin(phi, pp);
+                        }
+                    }
+                    if (sc.nonpos) mask |= kMaskNonpos;
+                    if (record) to_global<double>(D.dS)[node] = double(S.dpost);
+                }
+            } else if (own && cls != kNodeNone) {
+                // walls and lid: no collision, no limiter; stored at once
+                const unsigned ob = cl.own;
+                const bool corner = (xc == 0 || xc == nx - 1) && (yr == 0 || yr == ny - 1);
+                if (D.diffusive && !corner) {
+                    const int mx = xc == 0 ? 1 : (xc == nx - 1 ? -1 : 0);
+                    const int my = yr == 0 ? 1 : (yr == ny - 1 ? -1 : 0);
+                    diffusive_wall<T, QE>(dst, plane, row, ob, g, shift, my != 0 ? 0 : mx, my,
+                                          yr == ny - 1 ? A(D.lid_ux) : A(0));
+                } else if (cls == kNodeWall) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) Store<T>::st(at_bytes(dst + (i * plane + row), ob), g[L::opp(i)]);
+                } else {
+                    A E[Q];
+                    eq_excess<kD2Q9, QE>(A(D.lid_ux), A(0), E);
+                    const A r0 = A(D.rho0);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        Store<T>::st(at_bytes(dst + (i * plane + row), ob), A(L::w(i)) * ((r0 - shift) + r0 * E[i]));
+                }
+                double dr = 0, jx = 0, jy = 0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    dr += double(g[i]);
+                    jx += L::vx(i) * double(g[i]);
+                    jy += L::vy(i) * double(g[i]);
+                }
+                am += dr;
+                ax += jx;
+                ay += jy;
+                if (!(isfinite(dr) && isfinite(jx) && isfinite(jy))) ++acc.nonfin;
+                if (record) {
+                    to_global<unsigned char>(D.mask)[node] = (unsigned char)kMaskNotFluid;
+                    to_global<double>(D.dS)[node] = 0.0;
+                }
+            }
+            // this row's Delta S' with its neighbours' (every lane takes part)
+            A wn[3];
+            wn[1] = dcur;
+            wn[0] = lane_shift<-1>(dcur);
+            wn[2] = lane_shift<+1>(dcur);
+            // decide and store the row above (row y - 1)
+            const int yd = y - 1;
+            if (owned && yd >= t.y0 && yd < t.y1 && p_fluid) {
+                const int ydr = row_of(yd);
+                const long long drow = (long long)ydr * nx;
+                SiteState<kD2Q9, A> P;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    P.gs[i] = pend[i][tid];
+                    P.d[i] = pend[Q + i][tid];
+                }
+                P.dpost = p_dpost;
+                P.c = c;
+                P.posrule = false;
+                A thr;
+                if (median && median_hit<BC>(D, xc, ydr, nx, ny, wb, wm, wn, thr)) {
+                    p_mask |= kMaskMedian;
+                    ++acc.filt;
+                    A pm = A(1);
+                    bool done = false;
+                    if constexpr (DS == kExact) {
+                        if (D.homothety && isfinite(p_dpost)) {
+                            pm = exact_homothety_call(P, shift, thr, p_dpost);
+                            done = true;
+                        }
+                    }
+                    if (!done) pm = sqrt_(thr * rcp(p_dpost));
+                    p_phi = fmin(p_phi, pm);
+                }
+                store_limited<T>(dst, plane, drow, cl.own, P, p_phi, c);
+                if (p_mask & kMaskTrim) ++acc.trim;
+                if (p_phi < A(1) && isfinite(p_dpost)) acc.lim += double(p_dpost - delta_s_scaled<kD2Q9, DS>(P, shift, c, p_phi));
+                if (record) to_global<unsigned char>(D.mask)[unsigned(drow) + unsigned(xc)] = (unsigned char)p_mask;
+            }
+            // this row becomes the pending one
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                wb[k] = wm[k];
+                wm[k] = wn[k];
+            }
+            p_fluid = own && cls == kNodeFluid;
+            if (p_fluid) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    pend[i][tid] = S.gs[i];
+                    pend[Q + i][tid] = S.d[i];
+                }
+                p_dpost = S.dpost;
+                p_phi = phi;
+                p_mask = mask;
+            }
+        };
+        // rows y0 - 1 .. y1, the gathers of the next two rows in flight while a
+        // row is computed (a wave walks its rows alone, so its own loads are
+        // what hides the memory latency); three buffers used in turn, so no
+        // register copy waits for a load.  The gathers are unconditional
+        // (past the last row they repeat it and go unused): a load skipped on
+        // one path would make every use wait for all loads in flight.
+        auto fetch = [&](int y, A (&g)[Q]) { gather2d<BC>(src, plane, nx, ny, cl, row_of(y <= t.y1 ? y : t.y1), g); };
+        A ga[Q], gb[Q], gc[Q];
+        fetch(t.y0 - 1, ga);
+        fetch(t.y0, gb);
+        for (int y = t.y0 - 1;; y += 3) {
+            fetch(y + 2, gc);
+            do_row(y, ga);
+            if (y + 1 > t.y1) break;
+            fetch(y + 3, ga);
+            do_row(y + 1, gb);
+            if (y + 2 > t.y1) break;
+            fetch(y + 4, gb);
+            do_row(y + 2, gc);
+            if (y + 3 > t.y1) break;
+        }
+    }
+    AccT<double> tot;
+    tot.mass = am;
+    tot.jx = ax;
+    tot.jy = ay;
+    tot.dpre = double(acc.dpre);
+    tot.dpost = double(acc.dpost);
+    tot.maxd = double(acc.maxd);
+    tot.lim = acc.lim;
+    tot.ent = double(acc.ent);
+    tot.trim = acc.trim;
+    tot.filt = acc.filt;
+    tot.nonpos = acc.nonpos;
+    tot.nonfin = acc.nonfin;
+    tot.fluid = acc.fluid;
+    tot.pos = acc.pos;
+    store_partial(tot, partial_slot(a, 1, tidx), red);
+}
+
 // D1Q3: each workgroup computes Delta S' at kThreads consecutive sites and
 // updates the inner ones (3-point median, Sec. 4.3.2).
 template <int BC, class T>
@@ -975,6 +1254,8 @@ hipError_t LBM_CAT(launch_step2d, LBM_SUFFIX)(int qe, int ds, int bc, const Step
         LBM_DISPATCH(k_collide2d, 0, 1, dim3(a.nrows), dim3(kThreads), 0, s, a);
     else if (kernel == 2)
         LBM_DISPATCH_ELBM(k_collide2d, 0, 1, dim3(a.nrows), dim3(kThreads), 0, s, a);
+    else if (kernel == 3)
+        LBM_DISPATCH(k_fused2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     else if (a.ens_pass)
         LBM_DISPATCH(k_median_ens2d, 0, 1, dim3(a.ntiles), dim3(kThreads), 0, s, a);
     else

@@ -43,16 +43,17 @@ def say(*a):
 class Pair:
     """GPU and oracle results after `steps` steps from the same state."""
 
-    def __init__(self, dom, f0, steps=1, storage=0, tile=None, flags=None, entropy=False):
+    def __init__(self, dom, f0, steps=1, storage=0, tile=None, flags=None, entropy=False, tile_x=0):
         L = lbm()
         o = orc()
         say(f"[case] lattice={dom.lattice} n={dom.nx}x{dom.ny} bc={dom.bc} qe={dom.qe} ds={dom.ds_form} "
-            f"lim={dom.limiter} modes={dom.trim_mode}/{dom.median_mode} storage={storage} steps={steps} tile={tile}")
+            f"lim={dom.limiter} modes={dom.trim_mode}/{dom.median_mode} storage={storage} steps={steps} tile={tile} "
+            f"tile_x={tile_x}")
         dom.f_init = np.ascontiguousarray(f0)
         fl = L.LBM_RUN_RECORD | (L.LBM_RUN_ENTROPY if entropy else 0) if flags is None else flags
-        run = L.Run(storage=storage, flags=fl)
+        run = L.Run(storage=storage, flags=fl, tile_x=tile_x)
         if tile:
-            run.tile_h = int(tile)     # rows per D2Q9 wave tile
+            run.tile_h = int(tile)     # rows per D2Q9 second-pass (or fused) tile
         with L.lbm_create([dom], run) as ctx:
             self.tile = L.lbm_tile_config(ctx)
             L.lbm_step(ctx, steps)

@@ -176,19 +176,23 @@ def test_set_get_roundtrip_and_zero_steps(storage):
 
 @pytest.mark.parametrize("storage", [0, 1])
 def test_tile_shapes_give_identical_fields(storage):
-    """Per-site arithmetic does not depend on the tiling (catches halo/ring races)."""
+    """Per-site arithmetic does not depend on the tiling (catches halo/ring
+    races): the two-kernel step over second-pass tiles of 1 to 64 rows, and
+    the fused step over tiles of 1 to 128 rows, each bit for bit."""
     L = lbm()
     f0 = wl.random_populations(9, 300, 70, seed=77, amp=0.05, spike_frac=0.05, spike_amp=0.4)
-    outs = []
-    for tile in [1, 3, 8, 16, 64]:
-        d = dom2d(qe=1, ds_form=1 if storage else 0, limiter=3, f_init=f0)
-        run = L.Run(storage=storage, tile_h=tile, flags=L.LBM_RUN_RECORD)
-        with L.lbm_create([d], run) as ctx:
-            L.lbm_step(ctx, 5)
-            outs.append((L.lbm_get_populations(ctx), L.lbm_limiter_mask(ctx)[0]))
-    for f, m in outs[1:]:
-        assert np.array_equal(f, outs[0][0])
-        assert np.array_equal(m, outs[0][1])
+    for tile_x, tiles in ((256, [1, 3, 8, 16, 64]), (248, [1, 3, 32, 64, 128])):
+        outs = []
+        for tile in tiles:
+            d = dom2d(qe=1, ds_form=1 if storage else 0, limiter=3, f_init=f0)
+            run = L.Run(storage=storage, tile_x=tile_x, tile_h=tile, flags=L.LBM_RUN_RECORD)
+            with L.lbm_create([d], run) as ctx:
+                assert L.lbm_tile_config(ctx)[0] == tile_x and L.lbm_tile_config(ctx)[2] == tile
+                L.lbm_step(ctx, 5)
+                outs.append((L.lbm_get_populations(ctx), L.lbm_limiter_mask(ctx)[0]))
+        for f, m in outs[1:]:
+            assert np.array_equal(f, outs[0][0])
+            assert np.array_equal(m, outs[0][1])
 
 
 def test_repeat_runs_are_bitwise_identical():

@@ -1,9 +1,11 @@
 """The shapes the autotuner chooses between change the speed of a step and
-nothing it computes: row blocks of 256 columns or several rows of a narrow
-domain per workgroup, and the tile height of the second pass.  Fields, masks
-and the stats that come from the collision kernel (and E(Delta S'), which the
-ensemble limiters use) are bit-identical across shapes; the FP64 sums the
-second pass adds to agree to rounding."""
+nothing it decides: row blocks of 256 columns or several rows of a narrow
+domain per workgroup, the tile height of the second pass, and the fused step.
+Across the two-kernel shapes fields, masks and the stats that come from the
+collision kernel (and E(Delta S'), which the ensemble limiters use) are
+bit-identical, and the FP64 sums the second pass adds to agree to rounding;
+the fused step takes the same decisions and forms a moved node's state once,
+so its populations agree to rounding."""
 import numpy as np
 import pytest
 
@@ -53,12 +55,20 @@ def test_shapes_do_not_change_results(limiter, kw, storage):
     for tile_x, tile_h in ((64, 16), (64, 64), (256, 32), (0, 0)):
         shape, got = run(L, doms, storage, 12, tile_x, tile_h)
         say(f"[tuner] limiter={limiter} storage={storage} asked ({tile_x}, {tile_h}) -> shape {shape}")
+        fused = shape[0] == 248
         for (fa, ma, sa), (fb, mb, sb) in zip(ref, got):
-            assert np.array_equal(fa, fb)
             assert np.array_equal(ma, mb)
-            for k in COLLISION_STATS:
+            for k in ("n_trimmed", "n_filtered", "n_ensemble", "n_positivity", "n_fluid", "n_nonpositive"):
                 assert sa[k] == sb[k], k
-            for k in ("n_trimmed", "n_filtered", "n_ensemble", "n_positivity"):
+            if fused:
+                # the fused step forms a moved node's state once: rounding-level differences
+                scale = np.abs(fa).max()
+                assert np.abs(fa - fb).max() <= (1e-13 if storage == 0 else 2e-6) * scale
+                for k in ("mass", "sum_dS_post", "max_dS"):
+                    assert sb[k] == pytest.approx(sa[k], rel=1e-12 if storage == 0 else 1e-6, abs=1e-300), k
+                continue
+            assert np.array_equal(fa, fb)
+            for k in COLLISION_STATS:
                 assert sa[k] == sb[k], k
             assert sb["limiter_production"] == pytest.approx(sa["limiter_production"], rel=1e-12, abs=1e-300)
 
