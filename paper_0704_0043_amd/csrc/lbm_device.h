@@ -423,14 +423,23 @@ __device__ __forceinline__ void moments_equilibrium(const A (&g)[Lat<LAT>::Q], A
     ux = jx * inv;
     uy = jy * inv;
     if constexpr (QE == kPoly && fp32) {
-        // w_i (dr + rho (9 (v_i.u)^2 / 2 - 3 u^2 / 2)) + a_i v_i.j
+        // w_i (dr + rho (9 (v_i.u)^2 / 2 - 3 u^2 / 2)) + a_i v_i.j; a velocity
+        // and its opposite share the even part and take the odd one with
+        // opposite signs (v.u and v.j change sign exactly)
         const A base = A(-1.5) * (ux * ux + uy * uy);
+        auto dot = [](int vx, int vy, A x, A y) -> A {
+            const A xs = vx > 0 ? x : -x, ys = vy > 0 ? y : -y;
+            return vx == 0 ? ys : (vy == 0 ? xs : xs + ys);
+        };
+        gs[0] = A(L::w(0)) * (dr + rho * base);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const A cu = A(L::vx(i)) * ux + A(L::vy(i)) * uy;
-            const A cj = A(L::vx(i)) * jx + A(L::vy(i)) * jy;
+        for (int i = 1; i < Q; ++i) {
+            if (L::opp(i) < i) continue;   // each pair once, from its first member
+            const A cu = dot(L::vx(i), L::vy(i), ux, uy);
+            const A cj = dot(L::vx(i), L::vy(i), jx, jy);
             const A even = A(L::w(i)) * (dr + rho * (base + A(4.5) * cu * cu));
             gs[i] = __builtin_fmaf(mom_coef<LAT>(i), cj, even);
+            gs[L::opp(i)] = __builtin_fmaf(mom_coef<LAT>(i), -cj, even);
         }
         return;
     }
@@ -879,11 +888,12 @@ __device__ inline void node_partial_rows(const AccT<S>& acc, double* out, long l
     }
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const double cnt[8] = {double(__popcll(__ballot(acc.trim != 0))), double(__popcll(__ballot(acc.filt != 0))),
-                           double(__popcll(__ballot(acc.nonpos != 0))), double(__popcll(__ballot(acc.nonfin != 0))),
-                           double(__popcll(__ballot(acc.fluid != 0))),
-                           __ballot(acc.above != 0) ? double(1 << (wave % wpr)) : 0.0,
-                           double(__popcll(__ballot(acc.ens != 0))), double(__popcll(__ballot(acc.pos != 0)))};
+    // counts of a wave fit 32 bits; wpr is a power of two
+    auto count = [](bool b) { return double(unsigned(__popcll(__ballot(b)))); };
+    const double cnt[8] = {count(acc.trim != 0), count(acc.filt != 0), count(acc.nonpos != 0),
+                           count(acc.nonfin != 0), count(acc.fluid != 0),
+                           __ballot(acc.above != 0) ? double(1u << (unsigned(wave) & unsigned(wpr - 1))) : 0.0,
+                           count(acc.ens != 0), count(acc.pos != 0)};
     if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) lds[wave * kNStat + k] = double(v[k]);

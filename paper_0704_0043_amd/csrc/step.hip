@@ -225,12 +225,9 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
     // above delta stores nothing, and the median pass reads its 64 columns as
     // zeros (the segment's partial records which waves stored).
     const bool every = (D.limiter & kLimEns) || D.median_mode != 0;
-    // the block width is a power of two (64, 128 or 256)
-    const int lx = int(threadIdx.x) & (t.width - 1), ly = int(threadIdx.x) >> __builtin_ctz(unsigned(t.width));
-    const int y = t.y0 + ly;
-    const Cols<T, BC> cl(t.x0 + lx, nx, t.x0 + lx < t.x1 && y < t.y1);
     AccT<A> acc;
-    if (cl.ok) {
+    // the node (cl.x, y) of this thread
+    auto visit = [&](const int y, const Cols<T, BC>& cl) {
         {
             A g[Q];
             gather2d<BC>(src, plane, nx, ny, cl, y, g);
@@ -323,6 +320,19 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                 }
             }
         }
+    };
+    if (t.width == kThreads) {
+        // one row per block: its index is uniform, so are the row offsets
+        // of every load and store (scalar bases, 32-bit lane offsets)
+        const int x = t.x0 + int(threadIdx.x);
+        const Cols<T, BC> cl(x, nx, x < t.x1);
+        if (cl.ok) visit(t.y0, cl);
+    } else {
+        // a block of a narrow domain (its width a power of two: 64 or 128)
+        const int lx = int(threadIdx.x) & (t.width - 1), ly = int(threadIdx.x) >> __builtin_ctz(unsigned(t.width));
+        const int y = t.y0 + ly;
+        const Cols<T, BC> cl(t.x0 + lx, nx, t.x0 + lx < t.x1 && y < t.y1);
+        if (cl.ok) visit(y, cl);
     }
     // one partial per row of the block (row y, strip x0 / kThreads)
     node_partial_rows(acc, a.rowpart + ((long long)D.row_first + (long long)t.y0 * D.strips + t.x0 / kThreads) * kNStat,
