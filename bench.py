@@ -33,7 +33,9 @@ cavities run one by one).
 
 --hopf runs, instead of the benchmark, the first-Hopf-bifurcation experiment
 (a batch of 100 x 100 cavities with diffusive walls over a range of Re for
-5000 non-dimensional time units each) and prints its analysis.
+5000 non-dimensional time units each) and prints its analysis;
+--hopf-continuation its hysteresis test (continuation down from an
+oscillating state and up from a steady one).
 
 --summarize-pmc FETCH_CSV WRITE_CSV turns two rocprofv3 --pmc runs of this
 script (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy) into the HBM
@@ -472,6 +474,9 @@ def main():
     ap.add_argument("--hopf-re", default="6000:9000:250", help="Reynolds numbers, start:stop:step (inclusive)")
     ap.add_argument("--hopf-units", type=float, default=5000.0, help="non-dimensional time units per run")
     ap.add_argument("--hopf-n", type=int, default=100)
+    ap.add_argument("--hopf-continuation", action="store_true",
+                    help="instead of the benchmark: the hysteresis test of the Hopf onset (continuation down from "
+                         "an oscillating state, up from a steady one)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
@@ -490,6 +495,11 @@ def main():
         sys.exit(1)
     torch.cuda.init()
     stream = torch.cuda.Stream()
+    if args.hopf_continuation:
+        from paper_0704_0043_amd import hopf
+        res = hopf.continuation(L, n=args.hopf_n, stream=stream.cuda_stream)
+        print(json.dumps({"hopf_continuation": res}), flush=True)
+        return
     if args.hopf:
         from paper_0704_0043_amd import hopf
         a, b, c = (float(v) for v in args.hopf_re.split(":"))

@@ -54,7 +54,9 @@ extern "C" {
 #define LBM_EINVAL (-1)    /* invalid argument (sizes, beta, delta, enums, NULL) */
 #define LBM_ENOMEM (-2)    /* device allocation failed or workspace too small */
 #define LBM_EDEVICE (-3)   /* a HIP runtime error; message in lbm_last_error */
-#define LBM_EUNSTABLE (-4) /* non-finite moments seen at a stats point */
+#define LBM_EUNSTABLE (-4) /* at a stats point: non-finite moments, or, with the exact Delta S
+                              and neither trimming nor the positivity rule, a non-positive
+                              population (Delta S = +inf, eq. DelS undefined) */
 #define LBM_ERANGE (-5)    /* domain index out of range */
 
 /* lattice (Sec. 4.1) */
@@ -176,7 +178,7 @@ typedef struct {
     int32_t storage;            /* enum lbm_storage */
     int32_t device;             /* HIP device ordinal */
     int32_t stats_every;        /* >0: lbm_step synchronises every k steps and
-                                   returns LBM_EUNSTABLE on non-finite moments */
+                                   returns LBM_EUNSTABLE as lbm_entropy_stats does */
     int32_t tile_x;             /* D2Q9 collision row blocks (one node per thread, 256 per
                                    workgroup): 256 = one row of 256 columns per workgroup;
                                    64 = for a domain at most 128 wide, the narrowest of 64
@@ -262,7 +264,10 @@ LBM_API int lbm_synchronize(lbm_ctx* ctx);
 LBM_API int lbm_moments(lbm_ctx* ctx, int32_t domain, double* rho, double* u);
 
 /* sync.  Global sums of the last completed step (FP64).  Returns
- * LBM_EUNSTABLE (with *out filled) when n_nonfinite > 0. */
+ * LBM_EUNSTABLE (with *out filled) when n_nonfinite > 0, or when
+ * n_nonpositive > 0 in a domain with the exact Delta S and neither trimming
+ * nor the positivity rule (nothing sent those nodes back into the domain of
+ * the entropy). */
 LBM_API int lbm_entropy_stats(lbm_ctx* ctx, int32_t domain, lbm_entropy_stats_t* out);
 
 /* sync.  Current state f[Q][ny*nx] as FP64 (reduced storage is widened). */

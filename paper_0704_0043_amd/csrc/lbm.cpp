@@ -826,7 +826,14 @@ int read_stats(lbm_ctx* ctx, int32_t d, lbm_entropy_stats_t* out)
         const uint32_t keep = out->struct_size ? std::min<uint32_t>(out->struct_size, sizeof(s)) : sizeof(s);
         std::memcpy(out, &s, keep);
     }
-    return s.n_nonfinite > 0 ? fail(ctx, LBM_EUNSTABLE, "non-finite moments in the last step") : LBM_OK;
+    if (s.n_nonfinite > 0) return fail(ctx, LBM_EUNSTABLE, "non-finite moments in the last step");
+    // with the exact Delta S a non-positive population leaves the entropy
+    // undefined (Delta S = +inf); trimming and the positivity rule send such
+    // a node to f* (or back to the positive side) in the same step, without
+    // them the state stays outside the domain of the entropy
+    if (s.n_nonpositive > 0 && h.d.ds_form == LBM_DS_EXACT && !(h.d.limiter & (LBM_LIM_TRIM | LBM_LIM_POSITIVITY)))
+        return fail(ctx, LBM_EUNSTABLE, "non-positive populations with the exact Delta S and no limiter that resolves them");
+    return LBM_OK;
 }
 
 // Layout of lbm_step_static's arrays in the static scratch array: one
@@ -895,7 +902,7 @@ const char* lbm_strerror(int code)
     case LBM_EINVAL: return "invalid argument";
     case LBM_ENOMEM: return "out of device memory or workspace too small";
     case LBM_EDEVICE: return "HIP device error";
-    case LBM_EUNSTABLE: return "non-finite moments (unstable run)";
+    case LBM_EUNSTABLE: return "non-finite moments, or unresolved non-positive populations (unstable run)";
     case LBM_ERANGE: return "domain index out of range";
     }
     return "unknown error";

@@ -135,3 +135,48 @@ def run(L, re_values, n: int = 100, u0: float = 0.1, time_units: float = 5000.0,
         "wall_s": wall, "mlups": len(doms) * n * n * steps / wall / 1e6,
     })
     return out
+
+
+def continuation(L, re_osc: float = 6400.0, re_steady: float = 6200.0, down=(6300.0, 6100.0, 5900.0, 5600.0),
+                 up=(6300.0, 6500.0, 6700.0, 7000.0), n: int = 100, u0: float = 0.1, time_units: float = 3000.0,
+                 tail: float = 0.01, stream=None, chunk: int = 250000, log=sys.stderr) -> dict:
+    """Hysteresis test of the onset: run re_osc (oscillating from rest) and
+    re_steady (steady from rest) for `time_units`, then continue from the
+    oscillating state at each Re of `down` and from the steady state at each
+    Re of `up` (the state carried over, only nu changed) for as long again;
+    E_u^2 and the dominant frequency of the last `tail` of every run."""
+    steps = int(round(time_units * n / u0))
+    keep = max(2, int(round(tail * steps)))
+
+    def go(doms):
+        t0 = time.perf_counter()
+        rd = L.Run(storage=0, graph_chunk=100, probe_capacity=keep, tile_h=16,
+                   stream=stream if stream is not None else 0)
+        with L.lbm_create(doms, rd) as ctx:
+            done = 0
+            while done < steps:
+                k = min(chunk, steps - done)
+                L.lbm_step(ctx, k)
+                L.lbm_synchronize(ctx)
+                done += k
+                print(f"[hopf continuation] {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=log,
+                      flush=True)
+            sig = [L.lbm_probe_trace(ctx, k, keep)[:, 0] for k in range(len(doms))]
+            fs = [L.lbm_get_populations(ctx, k) for k in range(len(doms))]
+        return sig, fs
+
+    sig1, f1 = go(hopf_domains(L, [re_osc, re_steady], n, u0))
+    doms = []
+    for re, f in [(r, f1[0]) for r in down] + [(r, f1[1]) for r in up]:
+        d = hopf_domains(L, [re], n, u0)[0]
+        d.rho_init = d.u_init = None
+        d.f_init = np.ascontiguousarray(f)
+        doms.append(d)
+    sig2, _ = go(doms)
+    e2 = [energy(s, n, u0) ** 2 for s in sig2]
+    fr = [dominant_frequency(s, n, u0) for s in sig2]
+    nd = len(down)
+    return {"n": n, "u0": u0, "time_units_each": time_units, "tail": tail,
+            "from_rest": {"re": [re_osc, re_steady], "E_u2": [energy(s, n, u0) ** 2 for s in sig1]},
+            "down_from_oscillating": {"re": list(down), "E_u2": e2[:nd], "frequency": fr[:nd]},
+            "up_from_steady": {"re": list(up), "E_u2": e2[nd:], "frequency": fr[nd:]}}

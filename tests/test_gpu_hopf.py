@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_0704_0043_amd import hopf
-from tests.gpu_util import lbm, require_gpu, say
+from tests.gpu_util import lbm, orc, require_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -38,3 +38,34 @@ def test_probe_signal_is_the_node_velocity():
     # step; lbm_moments reports the state after it, one step later
     assert len(sig) == 64
     assert abs(sig[-1, 0] - u[0, py, px]) < 2e-3 * 0.1
+
+
+@pytest.mark.parametrize("re", [3000.0, 7375.0])
+def test_probe_trace_against_the_oracle(re):
+    """The Hopf setup (diffusive walls, entropic f*, exact Delta S, median
+    filter delta = 1e-3, FP64) on a 40 x 40 cavity from rest: the probe trace
+    of 600 steps, sample by sample, against the oracle's velocity at the
+    probe node before each step."""
+    L, o = lbm(), orc()
+    n, u0, steps = 40, 0.1, 600
+    d = hopf.hopf_domains(L, [re], n=n, u0=u0)[0]
+    px, py = hopf.probe_node(n)
+    with L.lbm_create([d], L.Run(storage=0, probe_capacity=steps)) as ctx:
+        L.lbm_step(ctx, steps)
+        sig = L.lbm_probe_trace(ctx, 0, steps)
+        st = L.lbm_entropy_stats(ctx)
+    p = o.make_params(lattice=2, nx=n, ny=n, beta=d.beta, qe=d.qe, ds_form=d.ds_form, limiter=d.limiter, bc=d.bc,
+                      delta_median=d.delta_median, rho0=d.rho0, lid_ux=d.lid_ux)
+    f = o.init_equilibrium(p, d.rho_init, d.u_init)
+    ref = np.empty((steps, 2))
+    filtered = 0
+    for k in range(steps):
+        _, ux, uy = o.moments(2, f)
+        ref[k] = ux[py, px], uy[py, px]
+        s, _, _ = o.step(p, f, 1, record=True)
+        filtered += s.n_filtered
+    err = np.abs(sig - ref)
+    say(f"[hopf probe Re={re:.0f}] max |u_gpu - u_oracle| {err.max():.2e} over {steps} samples; |u| up to "
+        f"{np.abs(ref).max():.3e}; filtered in the last step {st['n_filtered']} (oracle, all steps: {filtered})")
+    # the probe keeps FP32 samples of the FP64 velocity: one rounding
+    assert (err <= 2.0 ** -23 * np.abs(ref) + 1e-15).all()

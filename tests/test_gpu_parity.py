@@ -312,6 +312,28 @@ def test_batched_cavities_match_single_domain_oracle_runs():
         assert np.allclose(tr, np.array(probe, dtype=np.float32), rtol=1e-5, atol=1e-7)
 
 
+def test_nonpositive_state_with_exact_ds_is_unstable():
+    """A negative population with the exact Delta S: without trimming (or the
+    positivity rule) the stats point reports an unstable state; with trimming
+    the node goes to f* in the same step and the run stays valid."""
+    L = lbm()
+    f0 = wl.random_populations(9, 64, 32, seed=2, amp=0.05)
+    f0[3, 12, 20] = -0.01
+    for limiter, unstable in ((0, True), (2, True), (1, False), (3, False), (64, False)):
+        d = dom2d(nx=64, ny=32, qe=0, ds_form=0, limiter=limiter, f_init=f0.copy())
+        with L.lbm_create([d], L.Run(storage=0)) as ctx:
+            L.lbm_step(ctx, 1)
+            s = L.lbm_entropy_stats(ctx, allow_unstable=True)
+            say(f"[unstable] limiter={limiter} n_nonpositive={s['n_nonpositive']} unstable={bool(s.get('unstable'))}")
+            assert s["n_nonpositive"] > 0
+            assert bool(s.get("unstable")) == unstable
+    # the quadratic form needs only f* > 0: no error
+    d = dom2d(nx=64, ny=32, qe=0, ds_form=1, limiter=0, f_init=f0.copy())
+    with L.lbm_create([d], L.Run(storage=0)) as ctx:
+        L.lbm_step(ctx, 1)
+        assert not L.lbm_entropy_stats(ctx, allow_unstable=True).get("unstable")
+
+
 def test_unstable_state_is_reported():
     """A node with zero density makes u non-finite; the stats point reports it."""
     L = lbm()
