@@ -392,20 +392,21 @@ __device__ __forceinline__ bool median_hit(const DD& D, int x, int y, int nx, in
     return median_decide(D, c[1], med, thr);
 }
 
-// A node the second pass moves further: rescale the limited state that the
-// collision kernel stored at it toward its f*, rebuilt from the state's own
-// moments (the limiter kept them): f* + r (f_stored - f*), r = pq / pt (the
-// new factor over the applied one).  With the exact homothety the stored
-// state's deviation e = pt x is scaled to the target directly, and a direct
-// factor is taken relative to f' = f* + e / pt.  Returns the change of the
-// limiter's entropy production (Delta S of the stored state minus Delta S of
-// the new one).
-template <class T, int QE, int DS>
-__device__ __forceinline__ typename Store<T>::A rescale_stored(gptr<T> buf, long long plane, long long rc,
-                                                               unsigned own, typename Store<T>::A shift,
-                                                               typename Store<T>::A pq, typename Store<T>::A pt,
-                                                               typename Store<T>::A tgt, typename Store<T>::A fac,
-                                                               typename Store<T>::A dc, bool exact)
+// A node the second pass moves further with the exact Delta S: rescale the
+// limited state that the collision kernel stored at it toward its f*, rebuilt
+// from the state's own moments (the limiter kept them): f* + r (f_stored - f*),
+// r = pq / pt (the new factor over the applied one).  With the exact homothety
+// the stored state's deviation e = pt x is scaled to the target directly, and
+// a direct factor is taken relative to f' = f* + e / pt.  Returns the change of
+// the limiter's entropy production (Delta S of the stored state minus Delta S
+// of the new one).  A real call: its root solves would otherwise be inlined
+// into every unrolled row of the median walk, and the walk's window would no
+// longer fit in registers.  (The quadratic form rescales after each chunk's
+// decisions, in the walk itself.)
+template <class T, int QE>
+__device__ __attribute__((noinline)) typename Store<T>::A rescale_stored_exact(
+    gptr<T> buf, long long plane, long long rc, unsigned own, typename Store<T>::A shift, typename Store<T>::A pq,
+    typename Store<T>::A pt, typename Store<T>::A tgt, typename Store<T>::A fac, typename Store<T>::A dc, bool exact)
 {
     using A = typename Store<T>::A;
     constexpr int Q = 9;
@@ -416,29 +417,27 @@ __device__ __forceinline__ typename Store<T>::A rescale_stored(gptr<T> buf, long
     A dr, jx, jy, rho, ux, uy;
     moments_equilibrium<kD2Q9, QE>(gl, shift, dr, jx, jy, rho, ux, uy, gs);
     A r = pq * rcp(pt);
-    // deviation of the stored state (exact Delta S only)
-    A fs[DS == kExact ? Q : 1], e[DS == kExact ? Q : 1];
-    if constexpr (DS == kExact) {
+    // deviation of the stored state
+    A fs[Q], e[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        fs[i] = A(Lat<kD2Q9>::w(i)) * shift + gs[i];
+        e[i] = (gl[i] - gs[i]) * rcp(fs[i]);
+    }
+    if (exact) {
+        A ds_s = A(0), emin = A(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            fs[i] = A(Lat<kD2Q9>::w(i)) * shift + gs[i];
-            e[i] = (gl[i] - gs[i]) * rcp(fs[i]);
+            ds_s += fs[i] * hkern(e[i]);
+            emin = fmin(emin, e[i]);
         }
-        if (exact) {
-            A ds_s = A(0), emin = A(0);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                ds_s += fs[i] * hkern(e[i]);
-                emin = fmin(emin, e[i]);
-            }
-            r = A(1);
-            if (ds_s > A(0)) {
-                if (tgt < ds_s) r = kullback_scale<Q>(fs, e, tgt, sqrt_(tgt * rcp(ds_s)), A(0), A(1));
-                if (fac < A(1)) {
-                    const A lmax = emin < A(0) ? A(-1) / emin : A(__builtin_huge_val());
-                    const A lam = pt < A(1) ? kullback_scale<Q>(fs, e, dc, sqrt_(dc * rcp(ds_s)), A(1), lmax) : A(1);
-                    r = fmin(r, fac * lam);
-                }
+        r = A(1);
+        if (ds_s > A(0)) {
+            if (tgt < ds_s) r = kullback_scale<Q>(fs, e, tgt, sqrt_(tgt * rcp(ds_s)), A(0), A(1));
+            if (fac < A(1)) {
+                const A lmax = emin < A(0) ? A(-1) / emin : A(__builtin_huge_val());
+                const A lam = pt < A(1) ? kullback_scale<Q>(fs, e, dc, sqrt_(dc * rcp(ds_s)), A(1), lmax) : A(1);
+                r = fmin(r, fac * lam);
             }
         }
     }
@@ -447,33 +446,16 @@ __device__ __forceinline__ typename Store<T>::A rescale_stored(gptr<T> buf, long
 #pragma unroll
         for (int i = 0; i < Q; ++i) Store<T>::st(at_bytes(buf + (i * plane + rc), own), gs[i] + r * (gl[i] - gs[i]));
         if (isfinite(dc)) {
-            A ds_new, ds_old;
-            if constexpr (DS == kQuad) {
-                ds_new = r * r * pt * pt * dc;
-                ds_old = pt * pt * dc;
-            } else {
-                ds_new = ds_old = A(0);
+            A ds_new = A(0), ds_old = A(0);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    ds_old += fs[i] * hkern(e[i]);
-                    ds_new += fs[i] * hkern(r * e[i]);
-                }
+            for (int i = 0; i < Q; ++i) {
+                ds_old += fs[i] * hkern(e[i]);
+                ds_new += fs[i] * hkern(r * e[i]);
             }
             lim = ds_old - ds_new;
         }
     }
     return lim;
-}
-
-// the exact-form variant as a real call: its root solves would otherwise be
-// inlined into every unrolled row of the median walk, and the walk's window
-// would no longer fit in registers
-template <class T, int QE>
-__device__ __attribute__((noinline)) typename Store<T>::A rescale_stored_exact(
-    gptr<T> buf, long long plane, long long rc, unsigned own, typename Store<T>::A shift, typename Store<T>::A pq,
-    typename Store<T>::A pt, typename Store<T>::A tgt, typename Store<T>::A fac, typename Store<T>::A dc, bool exact)
-{
-    return rescale_stored<T, QE, kExact>(buf, plane, rc, own, shift, pq, pt, tgt, fac, dc, exact);
 }
 
 template <class T, int QE, int DS, int BC, bool ENS>
