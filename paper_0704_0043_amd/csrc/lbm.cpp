@@ -28,7 +28,7 @@ thread_local std::string g_err;
 
 constexpr size_t kAlign = 256;
 constexpr int kMinTuneH = 16;   // smallest median-tile height the tuner tries
-constexpr int kMinFusedH = 8;   // smallest fused-tile height the tuner tries
+constexpr int kMinFusedH = 4;   // smallest fused-tile height the tuner tries
 constexpr int kMaxFusedH = 128; // tallest fused tile
 
 // D2Q9 tiles: kThreads consecutive columns
@@ -675,7 +675,7 @@ int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
     // and the tuner cannot see how much of the flow the filter will move
     if (ctx->fuse_ok && run->tile_x == kFusedWidth) {
         const std::vector<int> fh = run->tile_h > 0 ? std::vector<int>{run->tile_h}
-                                                    : std::vector<int>{kMinFusedH, 16, 32, 64};
+                                                    : std::vector<int>{kMinFusedH, 8, 16, 32, 64};
         for (int th : fh) cand.push_back({widths[0], th, true});
     }
     ctx->tuned = 0;

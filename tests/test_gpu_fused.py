@@ -155,7 +155,8 @@ def test_fused_cavity_fp64(qe, diffusive):
 
 
 @pytest.mark.parametrize("nx,ny,th", [(40, 20, 32), (62, 33, 32), (63, 64, 64), (124, 31, 32), (125, 97, 96),
-                                      (247, 128, 128), (248, 65, 64), (249, 70, 32), (520, 129, 64)])
+                                      (247, 128, 128), (248, 65, 64), (249, 70, 32), (520, 129, 64),
+                                      (130, 9, 1), (250, 23, 3), (300, 42, 4)])
 def test_fused_ragged_sizes_against_two_kernels(nx, ny, th):
     f0 = wl.random_populations(9, nx, ny, seed=nx + ny, amp=0.05, spike_frac=0.05, spike_amp=0.4)
     compare_paths(dom(nx=nx, ny=ny, qe=1), f0, steps=1, tile_h=th)
