@@ -38,8 +38,9 @@ cavities run one by one).
 oscillating state and up from a steady one).
 
 --summarize-pmc FETCH_CSV WRITE_CSV turns two rocprofv3 --pmc runs of this
-script (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy) into the HBM
-traffic record the roofline reports.
+script (FETCH_SIZE, then WRITE_SIZE, with --calibrate-copy) into a table of
+each kernel's HBM bytes and the traffic record the roofline reports (not
+with --no-record).
 """
 from __future__ import annotations
 
@@ -398,10 +399,12 @@ def cavity_batch(torch, L, wl, stream, bsteps, one_by_one=False, kernel_steps=50
     return res
 
 
-def summarize_pmc(fetch_csv, write_csv):
-    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dominant kernel,
-    scaled by what the counters read for the calibration kernel (a plain
-    elementwise multiply of COPY_BYTES in, COPY_BYTES out)."""
+def summarize_pmc(fetch_csv, write_csv, record=True):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every kernel, scaled by
+    what the counters read for the calibration kernel (a plain elementwise
+    multiply of COPY_BYTES in, COPY_BYTES out), printed as a table; with
+    record, the dominant kernel's bytes are stored as the traffic record the
+    roofline reports."""
     def per_kernel(path, counter):
         out = {}
         with open(path) as fh:
@@ -425,6 +428,17 @@ def summarize_pmc(fetch_csv, write_csv):
     cal_w = pick(write, "MulFunctor", 3)
     sf = COPY_BYTES / (sum(cal_f) / len(cal_f))
     sw = COPY_BYTES / (sum(cal_w) / len(cal_w))
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetch MB (scaled) | write MB (scaled) |")
+    print("|---|---|---|---|---|---|")
+    for name, vf in fetch.items():
+        if "MulFunctor" in name:
+            continue
+        vw = write.get(name, [0.0])
+        mf, mw = sum(vf) / len(vf), sum(vw) / len(vw)
+        print(f"| {short_name(name)} | {len(vf)} | {mf / 1024:,.0f} | {mw / 1024:,.0f} | "
+              f"{sf * mf / 1e6:,.1f} | {sw * mw / 1e6:,.1f} |")
+    if not record:
+        return
     k_f = pick(fetch, DOMINANT)
     k_w = pick(write, DOMINANT)
     fb = sf * sum(k_f) / len(k_f)
@@ -436,6 +450,12 @@ def summarize_pmc(fetch_csv, write_csv):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def short_name(kernel):
+    """A kernel's name without its return type and parameter list."""
+    name = kernel.split("(")[0]
+    return name[5:] if name.startswith("void ") else name
 
 
 def np_arange_inclusive(a, b, c):
@@ -459,7 +479,7 @@ def main():
     ap.add_argument("--variants", action="store_true", help="also time FP16/BF16 8192^2 and the cavity ensemble")
     ap.add_argument("--tile-h", type=int, default=0, help="rows per second-pass tile (16, 32, 64; 0: tuned)")
     ap.add_argument("--tile-x", type=int, default=0,
-                    help="collision row blocks: 64 narrow, 256 full rows, 0 tuned (batch workload)")
+                    help="collision row blocks: 64 narrow, 256 full rows, 248 the fused step, 0 tuned")
     ap.add_argument("--delta-median", type=float, default=None,
                     help="median tolerance instead of 1e-4 (below the Delta S' of most nodes the filter acts)")
     ap.add_argument("--workload", choices=("headline", "elbm", "smooth", "batch"), default="headline",
@@ -469,6 +489,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--no-record", action="store_true",
+                    help="with --summarize-pmc: print the table only (a workload other than the headline)")
     ap.add_argument("--hopf", action="store_true",
                     help="instead of the step benchmark: the first-Hopf-bifurcation experiment (diffusive walls)")
     ap.add_argument("--hopf-re", default="6000:9000:250", help="Reynolds numbers, start:stop:step (inclusive)")
@@ -479,7 +501,7 @@ def main():
                          "an oscillating state, up from a steady one)")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, record=not args.no_record)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU path",
@@ -528,6 +550,8 @@ def main():
     run = L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)
     if args.tile_h:
         run.tile_h = args.tile_h
+    if args.tile_x:
+        run.tile_x = args.tile_x
     ctx = L.lbm_create([dom], run)
     tile = L.lbm_tile_config(ctx)
     # the per-kernel timing first: its warm-up brings the clocks to their

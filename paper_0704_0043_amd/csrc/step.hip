@@ -151,7 +151,11 @@ __device__ __forceinline__ void gather2d(gptr<const T> src, long long plane, int
     }
 }
 
-template <class T>
+// STREAM: the nontemporal hint, for a wave whose 64 lanes write whole
+// aligned row segments; a wave that writes a segment sharing its end sectors
+// with another wave's (the fused step) stores plainly, so that L2 merges the
+// two halves of a sector before it goes to HBM
+template <class T, bool STREAM = true>
 __device__ __forceinline__ void store_limited(gptr<T> dst, long long plane, long long row, unsigned own,
                                               const SiteState<kD2Q9, typename Store<T>::A>& S,
                                               typename Store<T>::A phi, typename Store<T>::A c)
@@ -159,7 +163,10 @@ __device__ __forceinline__ void store_limited(gptr<T> dst, long long plane, long
     using A = typename Store<T>::A;
     const A k = phi * c;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Store<T>::st_stream(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
+    for (int i = 0; i < 9; ++i) {
+        if constexpr (STREAM) Store<T>::st_stream(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
+        else Store<T>::st(at_bytes(dst + (i * plane + row), own), S.gs[i] - k * S.d[i]);
+    }
 }
 
 // Diffusive Maxwell wall node (Sec. 4.4.2), inward normal (mx, my), wall
@@ -942,7 +949,7 @@ __global__ void __launch_bounds__(kThreads) k_fused2d(StepArgs a)
                     if (!done) pm = sqrt_(thr * rcp(p_dpost));
                     p_phi = fmin(p_phi, pm);
                 }
-                store_limited<T>(dst, plane, drow, cl.own, P, p_phi, c);
+                store_limited<T, false>(dst, plane, drow, cl.own, P, p_phi, c);
                 if (p_mask & kMaskTrim) ++acc.trim;
                 if (p_phi < A(1) && isfinite(p_dpost)) acc.lim += double(p_dpost - delta_s_scaled<kD2Q9, DS>(P, shift, c, p_phi));
                 if (record) to_global<unsigned char>(D.mask)[unsigned(drow) + unsigned(xc)] = (unsigned char)p_mask;

@@ -79,6 +79,24 @@ def test_counter_summary_scales_by_the_calibration_kernel(tmp_path, monkeypatch)
     assert rec["kernel_hash"] == bench.kernel_hash()
 
 
+def test_counter_table_without_record(tmp_path, monkeypatch, capsys):
+    """--no-record prints every kernel's scaled bytes and leaves the record alone."""
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    cal = "void at::native::vectorized_elementwise_kernel<4, at::native::MulFunctor<float>>"
+    f = tmp_path / "fetch.csv"
+    w = tmp_path / "write.csv"
+    _csv(f, "FETCH_SIZE", [("void lbm::k_fused2d<float, 0, 1, 0>(lbm::StepArgs)", 1000)]
+         + [(cal, bench.COPY_BYTES // 2 // 1024)] * 3)
+    _csv(w, "WRITE_SIZE", [("void lbm::k_fused2d<float, 0, 1, 0>(lbm::StepArgs)", 500)]
+         + [(cal, bench.COPY_BYTES // 1024)] * 3)
+    bench.summarize_pmc(str(f), str(w), record=False)
+    text = capsys.readouterr().out
+    assert "| lbm::k_fused2d<float, 0, 1, 0> | 1 | 1,000 | 500 | 2.0 | 0.5 |" in text
+    assert "MulFunctor" not in text
+    assert not out.exists()
+
+
 def test_counter_summary_needs_the_calibration_kernel(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
     f = tmp_path / "fetch.csv"
