@@ -220,29 +220,33 @@ def kernel_times_warm(L, ctx, steps=50, warm_seconds=0.5):
                     "timed_steps": steps, "mode": "eager launches, HIP events on the context stream"}
 
 
-def median_active(torch, L, wl, stream, n, steps=200):
+def median_active(torch, L, wl, stream, n, steps=200, warmup=192):
     """The headline step with the median tolerance below the Delta S' of most
     nodes (delta_median = 1e-9, and 0): the filter moves a few percent (some
     fifteen percent) of the nodes every step.  Timed with the two kernels as
-    tuned (the second pass rescales the moved nodes' stored states) and with
-    the fused step (tile_x = 248, collision and filter in one pass)."""
+    tuned (the second pass rescales the moved nodes' stored states), with the
+    fused step (tile_x = 248, collision and filter in one pass), and adaptive
+    (LBM_RUN_ADAPTIVE: the two kernels first, the fused step from the second
+    64-step point on once the filter moves more than 0.5 % of the nodes),
+    each after `warmup` steps from the start."""
     sites = n * n
     out = {}
     for dmed in (1e-9, 0.0):
         res = {}
-        for name, tile_x in (("two_kernels", 0), ("fused", 248)):
+        for name, tile_x, flags in (("two_kernels", 0, 0), ("fused", 248, 0), ("adaptive", 0, L.LBM_RUN_ADAPTIVE)):
             dom = c2_domain(L, wl, n)
             dom.delta_median = dmed
-            with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, tile_x=tile_x)) as ctx:
+            with L.lbm_create([dom], L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, tile_x=tile_x,
+                                           flags=flags)) as ctx:
+                ms = time_steps(torch, L, ctx, stream, steps, warmup)
                 tile = L.lbm_tile_config(ctx)
-                ms = time_steps(torch, L, ctx, stream, steps, 16)
                 st = L.lbm_entropy_stats(ctx)
                 k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
             res[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
                          "tile": list(tile), "first_kernel_ms": round(k1, 5), "second_kernel_ms": round(k2, 5),
                          "filtered_fraction": round(st["n_filtered"] / sites, 4),
                          "step_hbm_frac": round(72 * sites / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        out[f"delta_median_{dmed:g}"] = dict(res, steps=steps)
+        out[f"delta_median_{dmed:g}"] = dict(res, steps=steps, warmup=warmup)
     return out
 
 
@@ -480,6 +484,8 @@ def main():
     ap.add_argument("--tile-h", type=int, default=0, help="rows per second-pass tile (16, 32, 64; 0: tuned)")
     ap.add_argument("--tile-x", type=int, default=0,
                     help="collision row blocks: 64 narrow, 256 full rows, 248 the fused step, 0 tuned")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="LBM_RUN_ADAPTIVE: two kernels or the fused step, chosen every 64 steps")
     ap.add_argument("--delta-median", type=float, default=None,
                     help="median tolerance instead of 1e-4 (below the Delta S' of most nodes the filter acts)")
     ap.add_argument("--workload", choices=("headline", "elbm", "smooth", "batch"), default="headline",
@@ -545,13 +551,15 @@ def main():
     elif args.workload == "smooth":
         dom.limiter |= L.LBM_LIM_ENS_SMOOTH
         dom.ens_k, dom.delta_ens = 0.5, 0.01
-    default = args.workload == "headline" and dmed == 1e-4
+    default = args.workload == "headline" and dmed == 1e-4 and not args.adaptive and args.tile_x in (0, 256)
     print(f"[bench] creating {n}x{n} FP32 context", file=sys.stderr, flush=True)
     run = L.Run(storage=L.LBM_F32, stream=stream.cuda_stream, graph_chunk=64)
     if args.tile_h:
         run.tile_h = args.tile_h
     if args.tile_x:
         run.tile_x = args.tile_x
+    if args.adaptive:
+        run.flags |= L.LBM_RUN_ADAPTIVE
     ctx = L.lbm_create([dom], run)
     tile = L.lbm_tile_config(ctx)
     # the per-kernel timing first: its warm-up brings the clocks to their

@@ -134,6 +134,23 @@ enum lbm_storage { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFT = 2, LBM_BF16_SHIFT =
 #define LBM_RUN_NO_GRAPH 4u  /* launch steps one by one (no captured graphs) */
 #define LBM_RUN_NO_TUNE 8u   /* no timing of shapes: narrow row blocks where a domain allows
                                 them, tile_h (or 64) for the second pass */
+#define LBM_RUN_ADAPTIVE 16u /* D2Q9 LBGK domains with the median filter and no ensemble-
+                                dependent limiter, tile_x other than 248: keep both forms of
+                                the step, the two kernels (shapes tuned as usual) and the
+                                fused step (tile height tuned; 8 rows with LBM_RUN_NO_TUNE),
+                                and choose between them while the run goes.  At every
+                                multiple of graph_chunk steps that lbm_step reaches, the
+                                number of nodes the median filter moved in the step just
+                                run is queued for reading back, and the form of the next
+                                graph_chunk steps is chosen from the number queued at the
+                                previous such point: the fused step once the filter moves
+                                more than 0.5 % of the fluid nodes, the two kernels again
+                                below 0.1 %; the two kernels first.  lbm_step then waits
+                                for the stream to pass the previous point (it runs at most
+                                about two chunks ahead).  The choice depends on the states
+                                at those steps only (not on how the steps are split into
+                                calls); the two forms take the same decisions and agree to
+                                rounding (see tile_x = 248).  Else LBM_EINVAL */
 
 /* One simulation domain.  All domains of one context share lattice, qe,
  * ds_form and bc (they run in the same kernel); sizes, beta, limiter and
@@ -253,7 +270,9 @@ LBM_API int lbm_create(const lbm_domain_desc* domains, int32_t n_domains,
                const lbm_run_desc* run, lbm_ctx** out);
 
 /* Advance every domain by n_steps >= 0 time steps (async, stream ordered),
- * as replays of the graphs captured at creation (unless LBM_RUN_NO_GRAPH). */
+ * as replays of the graphs captured at creation (unless LBM_RUN_NO_GRAPH).
+ * With LBM_RUN_ADAPTIVE it waits, at each multiple of graph_chunk steps,
+ * until the stream has passed the previous one. */
 LBM_API int lbm_step(lbm_ctx* ctx, int64_t n_steps);
 
 /* Wait for all queued work. */
@@ -286,10 +305,11 @@ LBM_API int lbm_limiter_mask(lbm_ctx* ctx, int32_t domain, uint8_t* mask, double
 LBM_API int lbm_probe_trace(lbm_ctx* ctx, int32_t domain, float* uv, int64_t max_samples,
                     int64_t* n_written);
 
-/* Shape in use.  D2Q9: columns of the first domain's collision row blocks
- * (256, or 64 / 128 for a narrow domain), their rows per workgroup, and the
- * rows of a second-pass tile; the fused step: 248, 1 and the rows of a fused
- * tile.  D1Q3: 254, 1, 1. */
+/* Shape in use (with LBM_RUN_ADAPTIVE, of the form the last step ran, or
+ * the next step runs after a choice).  D2Q9: columns of the first domain's
+ * collision row blocks (256, or 64 / 128 for a narrow domain), their rows
+ * per workgroup, and the rows of a second-pass tile; the fused step: 248, 1
+ * and the rows of a fused tile.  D1Q3: 254, 1, 1. */
 LBM_API int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_t* tile_h);
 
 /* sync; profiling aid outside the method.  Advances the state by n_steps

@@ -445,6 +445,31 @@ hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_d
     return hipGetLastError();
 }
 
+// The number of nodes the median filter moved in the step that read buffer
+// parity_done: the sum of the second-pass partials (set 1) of every tile,
+// which the two kernels and the fused step both write.  One workgroup, a
+// fixed order of the sums.
+__global__ void __launch_bounds__(kThreads) k_filtered_count(StepArgs a, int parity_done, double* out)
+{
+    __shared__ double red[kThreads];
+    const double* part = a.partials + ((long long)parity_done * 2 + 1) * a.pstride * kNStat;
+    double s = 0.0;
+    for (int t = int(threadIdx.x); t < a.ntiles; t += kThreads) s += part[(long long)t * kNStat + kSFilt];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w /= 2) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+hipError_t launch_filtered_count(const StepArgs& a, int parity_done, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_filtered_count, dim3(1), dim3(kThreads), 0, s, a, parity_done, out);
+    return hipGetLastError();
+}
+
 // f = f*(rho, u) at every node, FP64 (Sec. 4.1 quasiequilibria)
 template <int LAT, int QE>
 __global__ void k_init_f(const double* __restrict__ rho, const double* __restrict__ u, double* __restrict__ f,

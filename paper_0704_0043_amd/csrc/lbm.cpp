@@ -40,6 +40,25 @@ bool is_cavity(int bc) { return bc == LBM_BC_CAVITY || bc == LBM_BC_CAVITY_DIFFU
 bool is_topk(const lbm_domain_desc& d) { return (d.limiter & LBM_LIM_TRIM) && d.top_k > 0; }
 // limiters that need the whole domain's Delta S' before any node is limited
 bool deferred(const lbm_domain_desc& d) { return (d.limiter & kLimEns) || is_topk(d); }
+
+// the fused step applies: D2Q9 LBGK domains, the median filter in some, no
+// ensemble-dependent limiter (nor top-k trimming) in any
+bool fusable(const lbm_domain_desc* doms, int32_t nd)
+{
+    if (doms[0].lattice != LBM_D2Q9 || doms[0].collision == LBM_COLL_ELBM) return false;
+    bool median = false;
+    for (int k = 0; k < nd; ++k) {
+        if (deferred(doms[k])) return false;
+        median = median || (doms[k].limiter & LBM_LIM_MEDIAN);
+    }
+    return median;
+}
+
+// both forms of the step are kept and chosen between while the run goes
+bool adaptive_run(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
+{
+    return (run->flags & LBM_RUN_ADAPTIVE) && run->tile_x != kFusedWidth && fusable(doms, nd);
+}
 // the device limiter mask: top-k trimming moves to the second pass
 int device_limiter(const lbm_domain_desc& d)
 {
@@ -75,6 +94,7 @@ struct DomainHost {
 
 struct Layout {
     size_t off_dom = 0, off_tiles = 0, off_partials = 0, off_counter = 0, off_stage = 0, total = 0;
+    size_t off_dom_alt = 0, off_tiles_alt = 0, off_adapt = 0;   // LBM_RUN_ADAPTIVE only
     size_t off_rows = 0, off_rowpart = 0, off_groups = 0;
     int max_tiles = 0, nrows = 0, ngroups = 0;
     size_t max_n = 0;
@@ -93,12 +113,9 @@ struct lbm_ctx {
     Layout lay;
     char* ws = nullptr;
     bool own_ws = false;
-    int th = 16;            // rows per D2Q9 tile
-    int ntiles = 0;
     bool median_pass = false;   // D2Q9 with the median filter in some domain
     bool ens_pass = false;      // an ensemble-dependent limiter in some domain
     bool fuse_ok = false;       // the fused step applies (D2Q9 LBGK, median filter, no ensemble limiter)
-    bool fused = false;         // the fused step runs (tiles are fused tiles)
     bool budget = false;        // the budget threshold in some domain
     bool elbm = false;          // ELBM collisions (all domains)
     long long steps_done = 0, finalized_for = -1;
@@ -108,17 +125,40 @@ struct lbm_ctx {
         int64_t len;
         hipGraphExec_t exec;
     };
-    std::vector<StepGraph> graphs[2];
+    // One form of the step: the work tables it reads (tiles, and the domain
+    // views that hold each domain's tile range), in workspace regions of its
+    // own, and the graphs captured with them.  `act` runs the steps; with
+    // LBM_RUN_ADAPTIVE, `alt` holds the other form (the fused step or the two
+    // kernels) and the two trade places between chunks of steps.
+    struct Slot {
+        size_t off_dom = 0, off_tiles = 0;
+        int th = 16;                    // rows per D2Q9 tile
+        int ntiles = 0;
+        bool fused = false;             // the fused step (tiles are fused tiles)
+        std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
+        std::vector<DomainDev> dom_host;
+        std::vector<StepGraph> graphs[2];
+    };
+    Slot act, alt;
+    // LBM_RUN_ADAPTIVE: at every multiple of graph_chunk steps the filtered
+    // count of the step just run goes to pinned host memory (no wait), and
+    // the form of the next chunk is chosen from the count read back at the
+    // previous such point
+    bool adaptive = false;
+    double fluid_total = 0;             // fluid nodes of all domains
+    double* adapt_host = nullptr;       // [2] pinned
+    hipEvent_t adapt_ev[2] = {nullptr, nullptr};
+    bool adapt_pending[2] = {false, false};
+    long long adapt_points = 0, next_check = 0;
     std::string err;
-    std::vector<Tile> tiles_host;   // host copies kept alive for async uploads
     std::vector<RowBlock> rows_host;
     std::vector<Tile> groups_host;
     int narrow = 1;             // row blocks of 64 / 128 columns for narrow domains
     int tuned = 0;              // 1 when the tile shape was chosen by timing
-    std::vector<DomainDev> dom_host;
 
-    DomainDev* d_dom() const { return reinterpret_cast<DomainDev*>(ws + lay.off_dom); }
-    Tile* d_tiles() const { return reinterpret_cast<Tile*>(ws + lay.off_tiles); }
+    DomainDev* d_dom() const { return reinterpret_cast<DomainDev*>(ws + act.off_dom); }
+    Tile* d_tiles() const { return reinterpret_cast<Tile*>(ws + act.off_tiles); }
+    double* d_adapt() const { return reinterpret_cast<double*>(ws + lay.off_adapt); }
     RowBlock* d_rows() const { return reinterpret_cast<RowBlock*>(ws + lay.off_rows); }
     Tile* d_groups() const { return reinterpret_cast<Tile*>(ws + lay.off_groups); }
     double* d_rowpart() const { return reinterpret_cast<double*>(ws + lay.off_rowpart); }
@@ -239,6 +279,10 @@ int validate(const lbm_domain_desc* doms, int32_t nd, const lbm_run_desc* run)
                 }
         }
     }
+    if ((run->flags & LBM_RUN_ADAPTIVE) && (run->tile_x == kFusedWidth || !fusable(doms, nd)))
+        return fail(nullptr, LBM_EINVAL,
+                    "LBM_RUN_ADAPTIVE needs D2Q9 LBGK domains with the median filter and no "
+                    "ensemble-dependent limiter, and tile_x other than 248");
     return LBM_OK;
 }
 
@@ -280,6 +324,7 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     const size_t es = elem_size(storage);
     const unsigned flags = run->flags;
     const int cap = run->probe_capacity > 0 ? run->probe_capacity : 4096;
+    const bool adaptive = adaptive_run(doms, nd, run);
     size_t off = 0;
     L.max_tiles = 0;
     L.nrows = 0;
@@ -314,6 +359,8 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
         int tiles = tiles_of(h.d.lattice, h.d.nx, h.d.ny, min_h);
         if (h.d.lattice == LBM_D2Q9 && run->tile_x == kFusedWidth)
             tiles = std::max(tiles, fused_tiles_of(h.d.nx, h.d.ny, run->tile_h > 0 ? run->tile_h : kMinFusedH));
+        // adaptive: the fused tiles (any tuned height) share the partial slots
+        if (h.d.lattice == LBM_D2Q9 && adaptive) tiles = std::max(tiles, fused_tiles_of(h.d.nx, h.d.ny, kMinFusedH));
         L.max_tiles += tiles;
         L.ngroups += tiles_of(h.d.lattice, h.d.nx, h.d.ny, kMaxTileH);
         if (h.d.lattice == LBM_D2Q9) L.nrows += strips_of(h.d.nx) * h.d.ny;
@@ -323,6 +370,14 @@ void plan(std::vector<DomainHost>& dh, const lbm_domain_desc* doms, int32_t nd, 
     off = align_up(off + nd * sizeof(DomainDev), kAlign);
     L.off_tiles = off;
     off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
+    if (adaptive) {
+        L.off_dom_alt = off;
+        off = align_up(off + nd * sizeof(DomainDev), kAlign);
+        L.off_tiles_alt = off;
+        off = align_up(off + L.max_tiles * sizeof(Tile), kAlign);
+        L.off_adapt = off;
+        off = align_up(off + sizeof(double), kAlign);
+    }
     L.off_groups = off;
     off = align_up(off + L.ngroups * sizeof(Tile), kAlign);
     L.off_partials = off;
@@ -458,7 +513,7 @@ DomainDev make_dev(const DomainHost& h, char* base, void* b0, void* b1, int prob
 
 int upload_domains(lbm_ctx* ctx)
 {
-    std::vector<DomainDev>& dd = ctx->dom_host;
+    std::vector<DomainDev>& dd = ctx->act.dom_host;
     dd.assign(ctx->dom.size(), DomainDev{});
     for (size_t k = 0; k < ctx->dom.size(); ++k) {
         const DomainHost& h = ctx->dom[k];
@@ -471,12 +526,13 @@ int upload_domains(lbm_ctx* ctx)
 
 int set_tiles(lbm_ctx* ctx, int th, bool fused = false)
 {
-    ctx->tiles_host = build_tiles(ctx, th, fused);
-    ctx->fused = fused;
-    if (int(ctx->tiles_host.size()) > ctx->lay.max_tiles) return fail(ctx, LBM_EINVAL, "tile table overflow");
-    ctx->ntiles = int(ctx->tiles_host.size());
-    ctx->th = th;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tiles(), ctx->tiles_host.data(), ctx->tiles_host.size() * sizeof(Tile),
+    lbm_ctx::Slot& sl = ctx->act;
+    sl.tiles_host = build_tiles(ctx, th, fused);
+    sl.fused = fused;
+    if (int(sl.tiles_host.size()) > ctx->lay.max_tiles) return fail(ctx, LBM_EINVAL, "tile table overflow");
+    sl.ntiles = int(sl.tiles_host.size());
+    sl.th = th;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_tiles(), sl.tiles_host.data(), sl.tiles_host.size() * sizeof(Tile),
                                 hipMemcpyHostToDevice, ctx->stream));
     int rc = upload_domains(ctx);
     if (rc) return rc;
@@ -489,12 +545,12 @@ StepArgs step_args(const lbm_ctx* ctx, int parity)
     StepArgs a;
     a.dom = ctx->d_dom();
     a.tiles = ctx->d_tiles();
-    a.ntiles = ctx->ntiles;
+    a.ntiles = ctx->act.ntiles;
     a.ndomains = int(ctx->dom.size());
     a.median_pass = (ctx->median_pass || ctx->ens_pass) ? 1 : 0;
     a.ens_pass = ctx->ens_pass ? 1 : 0;
     a.budget = ctx->budget ? 1 : 0;
-    a.fused = ctx->fused ? 1 : 0;
+    a.fused = ctx->act.fused ? 1 : 0;
     a.rows = ctx->d_rows();
     a.nrows = int(ctx->rows_host.size());
     a.groups = ctx->d_groups();
@@ -550,7 +606,7 @@ hipError_t launch_step(const StepKind& k, const StepArgs& a, hipStream_t s, hipE
 StepKind step_kind(const lbm_ctx* ctx)
 {
     return StepKind{ctx->storage, ctx->lattice, ctx->qe, ctx->ds, ctx->bc, ctx->elbm, ctx->median_pass,
-                    ctx->ens_pass, ctx->budget, ctx->fused};
+                    ctx->ens_pass, ctx->budget, ctx->act.fused};
 }
 
 int launch_one(lbm_ctx* ctx, int parity, hipEvent_t* ev = nullptr, unsigned extra_flags = 0)
@@ -575,11 +631,12 @@ int reset_counters(lbm_ctx* ctx)
 
 void drop_graphs(lbm_ctx* ctx)
 {
-    for (auto& gs : ctx->graphs) {
-        for (auto& g : gs)
-            if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        gs.clear();
-    }
+    for (lbm_ctx::Slot* sl : {&ctx->act, &ctx->alt})
+        for (auto& gs : sl->graphs) {
+            for (auto& g : gs)
+                if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            gs.clear();
+        }
 }
 
 // ---- autotuner ---------------------------------------------------------------
@@ -654,7 +711,9 @@ int time_shape(lbm_ctx* ctx, int n, double& ms, unsigned extra_flags = 0)
     return rc;
 }
 
-int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
+// fused_alt: the fused form of an adaptive run (its tile height only; the
+// row blocks of the two-kernel form stay as tuned)
+int autotune(lbm_ctx* ctx, const lbm_run_desc* run, bool fused_alt = false)
 {
     bool any_narrow = false;
     for (const auto& h : ctx->dom) any_narrow = any_narrow || seg_width(h.d.nx, 1) < kThreads;
@@ -668,12 +727,15 @@ int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
     else if (second) heights = {16, 32, 64};
     else heights = {kMaxTileH};
     std::vector<Shape> cand;
-    if (run->tile_x != kFusedWidth)
+    if (fused_alt) {
+        for (int th : {kMinFusedH, 8, 16, 32, 64}) cand.push_back({ctx->narrow, th, true});
+        if (ctx->flags & LBM_RUN_NO_TUNE) return apply_shape(ctx, {ctx->narrow, 8, true});
+    } else if (run->tile_x != kFusedWidth)
         for (int w : widths)
             for (int th : heights) cand.push_back({w, th, false});
     // the fused step only when asked for: at creation no node has moved yet,
     // and the tuner cannot see how much of the flow the filter will move
-    if (ctx->fuse_ok && run->tile_x == kFusedWidth) {
+    if (!fused_alt && ctx->fuse_ok && run->tile_x == kFusedWidth) {
         const std::vector<int> fh = run->tile_h > 0 ? std::vector<int>{run->tile_h}
                                                     : std::vector<int>{kMinFusedH, 8, 16, 32, 64};
         for (int th : fh) cand.push_back({widths[0], th, true});
@@ -686,7 +748,7 @@ int autotune(lbm_ctx* ctx, const lbm_run_desc* run)
         if (run->tile_x == kFusedWidth) return apply_shape(ctx, {widths[0], run->tile_h > 0 ? run->tile_h : 64, true});
         return apply_shape(ctx, {widths[0], heights.back(), false});
     }
-    const std::string key = tune_key(ctx, run);
+    const std::string key = tune_key(ctx, run) + (fused_alt ? "/fused form" : "");
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -743,7 +805,7 @@ int capture(lbm_ctx* ctx, int parity, int64_t len)
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    ctx->graphs[parity].push_back({len, x});
+    ctx->act.graphs[parity].push_back({len, x});
     return LBM_OK;
 }
 
@@ -761,6 +823,45 @@ int capture_all(lbm_ctx* ctx)
             int rc = capture(ctx, parity, l);
             if (rc) return rc;
         }
+    return LBM_OK;
+}
+
+// Adaptive runs: the filtered fraction (nodes the median filter moved over
+// the fluid nodes of all domains) above which the fused step takes over, and
+// below which the two kernels come back.  The two kernels cost less while
+// few nodes move; once the filter moves a few per mille their second pass
+// reads and rewrites most sectors of the population planes again.
+constexpr double kAdaptOn = 5e-3;
+constexpr double kAdaptOff = 1e-3;
+
+// At a multiple of graph_chunk steps (or the first call past one): queue the
+// filtered count of the step just run for reading back without a wait, then
+// choose the form of the next chunk from the count queued at the previous
+// such point (which the stream has long passed).  The choice depends on the
+// states at those steps only, not on how the steps were split into calls.
+int adapt(lbm_ctx* ctx)
+{
+    if (ctx->steps_done < ctx->next_check) return LBM_OK;
+    const int slot = int(ctx->adapt_points % 2);
+    if (ctx->steps_done > 0) {
+        const StepArgs a = step_args(ctx, 0);
+        hipError_t e = launch_filtered_count(a, int((ctx->steps_done - 1) % 2), ctx->d_adapt(), ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->adapt_host + slot, ctx->d_adapt(), sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(ctx->adapt_ev[slot], ctx->stream);
+        if (e != hipSuccess) return fail(ctx, LBM_EDEVICE, std::string("filtered count: ") + hipGetErrorString(e));
+        ctx->adapt_pending[slot] = true;
+    }
+    if (ctx->adapt_pending[1 - slot]) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->adapt_ev[1 - slot]));
+        ctx->adapt_pending[1 - slot] = false;
+        const double frac = ctx->adapt_host[1 - slot] / std::max(ctx->fluid_total, 1.0);
+        if (ctx->act.fused ? frac < kAdaptOff : frac > kAdaptOn) std::swap(ctx->act, ctx->alt);
+    }
+    ++ctx->adapt_points;
+    const long long p = ctx->graph_chunk;
+    ctx->next_check = (ctx->steps_done / p + 1) * p;
     return LBM_OK;
 }
 
@@ -882,6 +983,9 @@ void release(lbm_ctx* ctx)
     if (!ctx) return;
     drop_graphs(ctx);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t& e : ctx->adapt_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->adapt_host) (void)hipHostFree(ctx->adapt_host);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -961,6 +1065,13 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
         return bail(fail(nullptr, LBM_EINVAL,
                          "tile_x = 248 (fused step) needs D2Q9 LBGK domains with the median filter and no "
                          "ensemble-dependent limiter"));
+    ctx->adaptive = adaptive_run(domains, n_domains, run);
+    ctx->act.off_dom = ctx->lay.off_dom;
+    ctx->act.off_tiles = ctx->lay.off_tiles;
+    ctx->alt.off_dom = ctx->lay.off_dom_alt;
+    ctx->alt.off_tiles = ctx->lay.off_tiles_alt;
+    for (const auto& h : ctx->dom)
+        ctx->fluid_total += is_cavity(h.d.bc) ? double(h.d.nx - 2) * double(h.d.ny - 2) : double(h.n);
     hipError_t e = hipSetDevice(run->device);
     if (e != hipSuccess) return bail(fail(nullptr, LBM_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e)));
     if (run->stream) {
@@ -1031,6 +1142,21 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
     // the tuner runs steps: the step counters must hold valid indices first
     rc = reset_counters(ctx);
     if (!rc) rc = ctx->lattice == LBM_D2Q9 ? autotune(ctx, run) : apply_shape(ctx, Shape{0, 1, false});
+    if (!rc && ctx->adaptive) {
+        // the fused form in the second set of tables; the two kernels run first
+        std::swap(ctx->act, ctx->alt);
+        rc = autotune(ctx, run, true);
+        std::swap(ctx->act, ctx->alt);
+        if (!rc && hipHostMalloc(reinterpret_cast<void**>(&ctx->adapt_host), 2 * sizeof(double)) != hipSuccess) {
+            ctx->adapt_host = nullptr;
+            rc = fail(ctx, LBM_ENOMEM, "hipHostMalloc");
+        }
+        for (hipEvent_t& ev : ctx->adapt_ev)
+            if (!rc && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                ev = nullptr;
+                rc = fail(ctx, LBM_EDEVICE, "hipEventCreate");
+            }
+    }
     if (rc) {
         g_err = ctx->err;
         return bail(rc);
@@ -1042,6 +1168,11 @@ int lbm_create(const lbm_domain_desc* domains, int32_t n_domains, const lbm_run_
             rc = fail(ctx, LBM_EDEVICE, "hipMemsetAsync stats");
     if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(ctx, LBM_EDEVICE, "sync after create");
     if (!rc && !(ctx->flags & LBM_RUN_NO_GRAPH)) rc = capture_all(ctx);
+    if (!rc && ctx->adaptive && !(ctx->flags & LBM_RUN_NO_GRAPH)) {
+        std::swap(ctx->act, ctx->alt);
+        rc = capture_all(ctx);
+        std::swap(ctx->act, ctx->alt);
+    }
     if (rc) {
         g_err = ctx->err;
         return bail(rc);
@@ -1057,12 +1188,15 @@ int lbm_step(lbm_ctx* ctx, int64_t n_steps)
     int64_t since_check = 0;
     while (n_steps > 0) {
         int rc;
+        if (ctx->adaptive && (rc = adapt(ctx))) return rc;
         int64_t done = 0;
         const int parity = int(ctx->steps_done % 2);
         // the longest captured sequence that fits before the next stats point
+        // (and, adaptive, before the next choice of the form)
         int64_t limit = n_steps;
         if (ctx->stats_every > 0) limit = std::min<int64_t>(limit, ctx->stats_every - since_check);
-        for (const auto& g : ctx->graphs[parity])
+        if (ctx->adaptive) limit = std::min<int64_t>(limit, ctx->next_check - ctx->steps_done);
+        for (const auto& g : ctx->act.graphs[parity])
             if (g.len <= limit) {
                 HIP_TRY(ctx, hipGraphLaunch(g.exec, ctx->stream));
                 done = g.len;
@@ -1201,10 +1335,11 @@ int lbm_tile_config(const lbm_ctx* ctx, int32_t* tile_x, int32_t* tile_y, int32_
     // narrow domain), their rows per workgroup, and the second pass's tile
     // height; D1Q3: sites per workgroup, 1, 1
     // height; the fused step reports kFusedWidth, 1 and its tile height
-    const int width = ctx->fused ? kFusedWidth : (d2 ? seg_width(ctx->dom[0].d.nx, ctx->narrow) : k1DWidth);
+    const bool fused = ctx->act.fused;
+    const int width = fused ? kFusedWidth : (d2 ? seg_width(ctx->dom[0].d.nx, ctx->narrow) : k1DWidth);
     if (tile_x) *tile_x = width;
-    if (tile_y) *tile_y = (d2 && !ctx->fused) ? kThreads / width : 1;
-    if (tile_h) *tile_h = d2 ? ctx->th : 1;
+    if (tile_y) *tile_y = (d2 && !fused) ? kThreads / width : 1;
+    if (tile_h) *tile_h = d2 ? ctx->act.th : 1;
     return LBM_OK;
 }
 
@@ -1239,7 +1374,7 @@ int lbm_kernel_times(lbm_ctx* ctx, int64_t n_steps, double* ms)
         if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     ms[0] = t[0] / double(n_steps);
-    ms[1] = ((ctx->median_pass || ctx->ens_pass) && !ctx->fused) ? t[1] / double(n_steps) : 0.0;
+    ms[1] = ((ctx->median_pass || ctx->ens_pass) && !ctx->act.fused) ? t[1] / double(n_steps) : 0.0;
     return LBM_OK;
 }
 

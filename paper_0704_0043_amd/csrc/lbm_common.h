@@ -245,6 +245,8 @@ hipError_t launch_ens_prepare(const StepArgs& a, hipStream_t s);
 // the budget threshold of the step just run (after launch_ens_prepare)
 hipError_t launch_budget(int storage, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_finalize(const StepArgs& a, int parity_done, long long steps_done, hipStream_t s);
+// nodes moved by the median filter in the step that read buffer parity_done -> out[0]
+hipError_t launch_filtered_count(const StepArgs& a, int parity_done, double* out, hipStream_t s);
 hipError_t launch_init_f(int lattice, int qe, const double* rho, const double* u, double* f, int nx, int ny,
                          hipStream_t s);
 hipError_t launch_scatter(int storage, int lattice, int bc, const double* f, void* buf, long long plane, int nx,

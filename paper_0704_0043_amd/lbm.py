@@ -38,7 +38,7 @@ LBM_BC_PERIODIC, LBM_BC_CAVITY, LBM_BC_TUBE_ENDS, LBM_BC_CAVITY_DIFFUSIVE = 0, 1
 LBM_F64, LBM_F32, LBM_F16_SHIFT, LBM_BF16_SHIFT = 0, 1, 2, 3
 LBM_MASK_TRIM, LBM_MASK_MEDIAN, LBM_MASK_NONPOS, LBM_MASK_NOTFLUID, LBM_MASK_ENSEMBLE = 1, 2, 4, 8, 16
 LBM_MASK_POSITIVITY = 32
-LBM_RUN_RECORD, LBM_RUN_ENTROPY, LBM_RUN_NO_GRAPH, LBM_RUN_NO_TUNE = 1, 2, 4, 8
+LBM_RUN_RECORD, LBM_RUN_ENTROPY, LBM_RUN_NO_GRAPH, LBM_RUN_NO_TUNE, LBM_RUN_ADAPTIVE = 1, 2, 4, 8, 16
 
 STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16_SHIFT: 2, LBM_BF16_SHIFT: 2}
 

@@ -119,6 +119,31 @@ def test_invalid_descriptors_are_rejected_before_any_device_call(L, bad):
     assert e.value.code == L.LBM_EINVAL
 
 
+@pytest.mark.parametrize("dom,run", [
+    (dict(limiter=1), dict()),                               # no median filter
+    (dict(limiter=2 | 8, ens_k=0.5), dict()),                # an ensemble-dependent limiter
+    (dict(limiter=2, collision=1, qe=1), dict()),            # ELBM
+    (dict(lattice=1, ny=1, limiter=2), dict()),              # D1Q3
+    (dict(limiter=2), dict(tile_x=248)),                     # the fused step already
+])
+def test_adaptive_runs_need_both_forms_of_the_step(L, dom, run):
+    kw = dict(nx=32, ny=16)
+    kw.update(dom)
+    r = L.Run(flags=L.LBM_RUN_ADAPTIVE, **run)
+    for call in (L.lbm_workspace_bytes, L.lbm_create):
+        with pytest.raises(L.LbmError) as e:
+            call([L.Domain(**kw)], r)
+        assert e.value.code == L.LBM_EINVAL
+
+
+def test_adaptive_workspace_holds_the_second_form(L):
+    """the fused form's tables (and its partial slots at 4-row tiles) come on top"""
+    d = [L.Domain(nx=300, ny=70, limiter=3)]
+    plain = L.lbm_workspace_bytes(d, L.Run())
+    adaptive = L.lbm_workspace_bytes(d, L.Run(flags=L.LBM_RUN_ADAPTIVE))
+    assert adaptive > plain
+
+
 def test_mixed_batches_are_rejected(L):
     with pytest.raises(L.LbmError):
         L.lbm_workspace_bytes([L.Domain(qe=0), L.Domain(qe=1)], L.Run())
