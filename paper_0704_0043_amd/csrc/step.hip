@@ -139,14 +139,32 @@ __device__ __forceinline__ void gather2d(gptr<const T> src, long long plane, int
             g[i] = Store<T>::ld(at_bytes(src + (i * plane + rs), cs));
         }
     } else {
+        // A wave covers one row (callers keep it so), so the source rows are
+        // scalars, clamped at the domain's edges like the lanes' columns; the
+        // loads are then those of the periodic case.  A source off the domain
+        // (at wall and lid nodes only) is replaced by the node's own opposite
+        // population, loaded afterwards for those lanes alone.
+        const int yw = __builtin_amdgcn_readfirstlane(y);
+        const long long r0 = (long long)yw * nx;
+        const long long rm = yw > 0 ? r0 - nx : r0;
+        const long long rp = yw < ny - 1 ? r0 + nx : r0;
+        constexpr unsigned es = sizeof(T);
         const int x = cl.x;
+        const unsigned cc = es * unsigned(x);
+        const unsigned cm = x > 0 ? cc - es : cc;
+        const unsigned cp = x < nx - 1 ? cc + es : cc;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const int xs = x - L::vx(i), ys = y - L::vy(i);
-            const bool in = xs >= 0 && xs < nx && ys >= 0 && ys < ny;
-            const long long off = in ? (i * plane + (long long)ys * nx + xs)
-                                     : (L::opp(i) * plane + (long long)y * nx + x);
-            g[i] = Store<T>::ld(src + off);
+            const long long rs = L::vy(i) > 0 ? rm : (L::vy(i) < 0 ? rp : r0);
+            const unsigned cs = L::vx(i) > 0 ? cm : (L::vx(i) < 0 ? cp : cc);
+            g[i] = Store<T>::ld(at_bytes(src + (i * plane + rs), cs));
+        }
+        const bool xm = x > 0, xp = x < nx - 1, ym = yw > 0, yp = yw < ny - 1;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const bool in = (L::vx(i) > 0 ? xm : (L::vx(i) < 0 ? xp : true)) &&
+                            (L::vy(i) > 0 ? ym : (L::vy(i) < 0 ? yp : true));
+            if (!in) g[i] = Store<T>::ld(at_bytes(src + (L::opp(i) * plane + r0), cc));
         }
     }
 }
@@ -335,7 +353,8 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
         const Cols<T, BC> cl(x, nx, x < t.x1);
         if (cl.ok) visit(t.y0, cl);
     } else {
-        // a block of a narrow domain (its width a power of two: 64 or 128)
+        // a block of a narrow domain (its width a power of two: 64 or 128,
+        // so that a wave never spans two rows, as the cavity gather needs)
         const int lx = int(threadIdx.x) & (t.width - 1), ly = int(threadIdx.x) >> __builtin_ctz(unsigned(t.width));
         const int y = t.y0 + ly;
         const Cols<T, BC> cl(t.x0 + lx, nx, t.x0 + lx < t.x1 && y < t.y1);
