@@ -126,13 +126,15 @@ def test_shear_layer_replica_error(storage):
     assert r["stats"]["n_nonfinite"] == 0
 
 
-def test_full_size_sampled_parity():
+@pytest.mark.parametrize("tile_x", [0, 248], ids=["two_kernels", "fused"])
+def test_full_size_sampled_parity(tile_x):
     """4096 x 4096, FP32, autotuned tiles and graph chunks as in the
-    benchmark: four steps from the seeded equilibrium (rounded to FP32 shift
-    storage on the host), then populations at sampled nodes against the
-    oracle run on a periodic 25 x 25 window around each node.  One step
-    reaches two nodes out (free flight, then the 3x3 median of Delta S'), so
-    after k = 4 steps the centre of the window does not see its seam."""
+    benchmark (and the fused step, tile_x = 248, with its tuned tile height):
+    four steps from the seeded equilibrium (rounded to FP32 shift storage on
+    the host), then populations at sampled nodes against the oracle run on a
+    periodic 25 x 25 window around each node.  One step reaches two nodes out
+    (free flight, then the 3x3 median of Delta S'), so after k = 4 steps the
+    centre of the window does not see its seam."""
     L, o = lbm(), orc()
     n, steps, r = 4096, 4, 12
     rho, u = wl.taylor_green(n, u0=0.05, mode=1, perturb=1e-3, seed=wl.DEFAULT_SEED)
@@ -144,15 +146,18 @@ def test_full_size_sampled_parity():
     # the state the FP32 shifted storage holds
     f0 = (f0 - W9[:, None, None]).astype(np.float32).astype(np.float64) + W9[:, None, None]
     dom.f_init = f0
-    with L.lbm_create([dom], L.Run(storage=L.LBM_F32, graph_chunk=64)) as ctx:
+    with L.lbm_create([dom], L.Run(storage=L.LBM_F32, graph_chunk=64, tile_x=tile_x)) as ctx:
         dom.f_init = None
         say(f"[full size] tile {L.lbm_tile_config(ctx)}")
+        assert (L.lbm_tile_config(ctx)[0] == 248) == (tile_x == 248)
         L.lbm_step(ctx, steps)
         fg = L.lbm_get_populations(ctx)
         st = L.lbm_entropy_stats(ctx)
     rng = wl.uniform(0x5A3, 128).reshape(64, 2)
     pts = [(int(a * n), int(b * n)) for a, b in rng]
     pts += [(0, 0), (n - 1, n - 1), (255, 63), (256, 64), (n - 1, 0), (0, n - 1), (2048, 2047)]
+    # fused tile seams: 62-column wave pieces, 248-column workgroups, 8-row tiles
+    pts += [(61, 7), (62, 8), (247, 15), (248, 16), (4091, 4095), (4092, 4088)]
     pw = o.make_params(lattice=2, nx=2 * r + 1, ny=2 * r + 1, beta=dom.beta, qe=0, ds_form=1, limiter=3,
                        delta_trim=1e-4, delta_median=1e-4, bc=0)
     worst = 0.0
