@@ -571,7 +571,12 @@ __device__ __forceinline__ void second_pass2d(const StepArgs& a)
             __syncthreads();
         }
     }
-    if (active && x < t.x1) {
+    // nothing to filter in this tile: its partial is zero (no reduction)
+    if (!active) {
+        if (threadIdx.x < kNStat) partial_slot(a, 1, tidx)[threadIdx.x] = 0.0;
+        return;
+    }
+    if (x < t.x1) {
         const long long plane = D.plane;
         const gptr<const A> dsb = to_global<A>(static_cast<const void*>(D.dsbuf));
         const A shift = A(D.shift);
