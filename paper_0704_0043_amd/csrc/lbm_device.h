@@ -469,9 +469,16 @@ __device__ __forceinline__ void moments_equilibrium(const A (&g)[Lat<LAT>::Q], A
         float dre, jxe, jye;
         comp_moments<LAT>(gs, dre, jxe, jye);
         const float dd = dr - dre, dx = jx - jxe, dy = jy - jye;
+        // v_i . (dx, dy) by signs (the components are 0 or +-1): the same
+        // values as the products, without multiplying by them
+        auto vdot = [&](int i) -> A {
+            const int vx = L::vx(i), vy = L::vy(i);
+            const A xs = vx > 0 ? dx : -dx, ys = vy > 0 ? dy : -dy;
+            return vx == 0 ? (vy == 0 ? A(0) : ys) : (vy == 0 ? xs : xs + ys);
+        };
+        gs[0] += A(L::w(0)) * dd;
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            gs[i] += A(L::w(i)) * dd + mom_coef<LAT>(i) * (A(L::vx(i)) * dx + A(L::vy(i)) * dy);
+        for (int i = 1; i < Q; ++i) gs[i] += A(L::w(i)) * dd + mom_coef<LAT>(i) * vdot(i);
     }
 }
 

@@ -169,6 +169,27 @@ __device__ __forceinline__ void gather2d(gptr<const T> src, long long plane, int
     }
 }
 
+// Mass and momentum of a wall or lid node's nine populations in FP64 (its
+// share of the stats), in population order; each population enters the
+// momentum sums only where its velocity component is nonzero.
+template <class A>
+__device__ __forceinline__ void moments_fp64(const A (&g)[9], double& dr, double& jx, double& jy)
+{
+    using L = Lat<kD2Q9>;
+    dr = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double v = double(g[i]);
+        dr += v;
+        if (L::vx(i) > 0) jx += v;
+        if (L::vx(i) < 0) jx -= v;
+        if (L::vy(i) > 0) jy += v;
+        if (L::vy(i) < 0) jy -= v;
+    }
+}
+
 // STREAM: the nontemporal hint, for a wave whose 64 lanes write whole
 // aligned row segments; a wave that writes a segment sharing its end sectors
 // with another wave's (the fused step) stores plainly, so that L2 merges the
@@ -328,16 +349,7 @@ __global__ void __launch_bounds__(kThreads) k_collide2d(StepArgs a)
                         Store<T>::st(at_bytes(dst + (i * plane + row), cl.own), A(L::w(i)) * ((r0 - shift) + r0 * E[i]));
                 }
                 SiteScalars sc;
-                double dr = 0, jx = 0, jy = 0;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    dr += double(g[i]);
-                    jx += L::vx(i) * double(g[i]);
-                    jy += L::vy(i) * double(g[i]);
-                }
-                sc.dr = dr;
-                sc.jx = jx;
-                sc.jy = jy;
+                moments_fp64(g, sc.dr, sc.jx, sc.jy);
                 acc.moments(sc);
                 if (record) {
                     to_global<unsigned char>(D.mask)[node] = (unsigned char)kMaskNotFluid;
@@ -923,13 +935,8 @@ __global__ void __launch_bounds__(kThreads) k_fused2d(StepArgs a)
                     for (int i = 0; i < Q; ++i)
                         Store<T>::st(at_bytes(dst + (i * plane + row), ob), A(L::w(i)) * ((r0 - shift) + r0 * E[i]));
                 }
-                double dr = 0, jx = 0, jy = 0;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    dr += double(g[i]);
-                    jx += L::vx(i) * double(g[i]);
-                    jy += L::vy(i) * double(g[i]);
-                }
+                double dr, jx, jy;
+                moments_fp64(g, dr, jx, jy);
                 am += dr;
                 ax += jx;
                 ay += jy;
