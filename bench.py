@@ -17,9 +17,9 @@ kernel's average duration, measured with HIP events on its stream after half
 a second of graph steps has brought the clocks to their sustained level; this
 measurement runs before the warm-up and timed steps); the roofline of the
 whole step; the same step with the
-median filter moving a few (delta_median = 1e-9) and some fifteen percent
-(delta_median = 0) of the nodes, with the two kernels and with the fused
-step; the
+median filter moving a few (delta_median = 1e-9) and some ten percent
+(delta_median = 0) of the nodes, with the two kernels, with the fused step
+and adaptively (LBM_RUN_ADAPTIVE); the
 max-norm error of a 1024 x 1024 replica against the FP64 CPU oracle; and that
 oracle timed on the host on the replica (its OpenMP build on the host's cores,
 and one thread).
