@@ -179,7 +179,12 @@ struct Store<__bf16> {
     using A = float;
     __device__ static A ld(gptr<const __bf16> p) { return float(*p); }
     __device__ static void st(gptr<__bf16> p, A v) { *p = (__bf16)v; }
-    __device__ static void st_stream(gptr<__bf16> p, A v) { st(p, v); }
+    // the nontemporal store of the 16-bit pattern (the builtin takes no __bf16)
+    __device__ static void st_stream(gptr<__bf16> p, A v)
+    {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (__bf16)v),
+                                    reinterpret_cast<gptr<unsigned short>>(p));
+    }
 };
 
 // ---- arithmetic helpers ------------------------------------------------------
