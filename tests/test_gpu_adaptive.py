@@ -134,6 +134,32 @@ def test_choices_do_not_depend_on_how_the_steps_are_called():
     assert np.array_equal(fa, fc)
 
 
+def test_adaptive_with_stats_checks_and_kernel_timing():
+    """stats read every 5 steps inside lbm_step, and eager steps of
+    lbm_kernel_times between calls: the same states as a plain adaptive run
+    over the same steps (the checks only read; the timed steps are steps)"""
+    L = lbm()
+    d = dom(nx=200, ny=45)
+    f0 = spiky(200, 45, seed=9)
+    say("[case] adaptive with stats_every = 5 and lbm_kernel_times, 200x45, chunk 8")
+    d.f_init = np.ascontiguousarray(f0)
+    with L.lbm_create([d], L.Run(storage=0, graph_chunk=8, stats_every=5, flags=L.LBM_RUN_ADAPTIVE)) as a:
+        L.lbm_step(a, 30)
+        L.lbm_kernel_times(a, 4)
+        L.lbm_step(a, 6)
+        fa = L.lbm_get_populations(a)
+        ta = L.lbm_tile_config(a)
+    d.f_init = None
+    with create(d, f0) as b:
+        L.lbm_step(b, 30)
+        L.lbm_kernel_times(b, 4)
+        L.lbm_step(b, 6)
+        fb = L.lbm_get_populations(b)
+        tb = L.lbm_tile_config(b)
+    assert ta == tb
+    assert np.array_equal(fa, fb)
+
+
 def test_adaptive_fp32_cavity_batch():
     """two cavities of different sizes in one FP32 batch (Sec. 4.4, entropic
     f*, median filter): the adaptive run stays with the plain run to the
