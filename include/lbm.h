@@ -216,7 +216,7 @@ typedef struct {
     int32_t tile_h;             /* rows per D2Q9 second-pass tile (1..64); 0 = chosen by the
                                    autotuner among 16, 32 and 64 (64 without a second pass).
                                    With tile_x = 248: rows per fused tile (1..128), 0 = chosen
-                                   among 8, 16, 32 and 64 */
+                                   among 4, 8, 16, 32 and 64 */
     uint32_t flags;             /* LBM_RUN_* */
     int32_t probe_capacity;     /* samples kept per probe (ring buffer), 0 = 4096 */
     int32_t graph_chunk;        /* longest captured step sequence, 1..4096, 0 = 64: lbm_create
