@@ -276,21 +276,29 @@ def copy_calibration(torch, stream, nbytes=COPY_BYTES, reps=3):
     return {"bytes_read": nbytes, "bytes_written": nbytes, "launches": reps}
 
 
+def shear_run(torch, L, wl, stream, storage, steps, warmup=16):
+    """The 8192^2 double shear layer (trimming only) in one storage type."""
+    dom = shear_domain(L, wl)
+    with L.lbm_create([dom], L.Run(storage=storage, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
+        ms = time_steps(torch, L, ctx, stream, steps, warmup)
+        k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
+    sites = dom.nx * dom.ny
+    b = BYTES_PER_SITE[storage] * sites
+    return {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
+            "step_hbm_frac": round(b / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "collide_ms": round(k1, 5), "steps": steps}
+
+
+SHEAR_STORAGE = {"shear-f32": "f32", "shear-f16": "f16", "shear-bf16": "bf16"}
+
+
 def variants(torch, L, wl, stream, args):
     res = {}
     steps = max(50, args.steps // 4)
     shear = {}
     for name, storage in (("f32", L.LBM_F32), ("f16", L.LBM_F16_SHIFT), ("bf16", L.LBM_BF16_SHIFT)):
         print(f"[bench] variant shear 8192^2 {name}", file=sys.stderr, flush=True)
-        dom = shear_domain(L, wl)
-        with L.lbm_create([dom], L.Run(storage=storage, stream=stream.cuda_stream, graph_chunk=64)) as ctx:
-            ms = time_steps(torch, L, ctx, stream, steps, 16)
-            k1, k2, _ = kernel_times_warm(L, ctx, 20, 0.2)
-        sites = dom.nx * dom.ny
-        b = BYTES_PER_SITE[storage] * sites
-        shear[name] = {"mlups": round(sites * steps / (ms * 1e3), 1), "ms_per_step": round(ms / steps, 5),
-                       "step_hbm_frac": round(b / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                       "collide_ms": round(k1, 5), "steps": steps}
+        shear[name] = shear_run(torch, L, wl, stream, storage, steps)
     for name in ("f16", "bf16"):
         shear[name]["vs_f32"] = round(shear[name]["mlups"] / shear["f32"]["mlups"], 3)
     res["shear_8192"] = shear
@@ -488,10 +496,12 @@ def main():
                     help="LBM_RUN_ADAPTIVE: two kernels or the fused step, chosen every 64 steps")
     ap.add_argument("--delta-median", type=float, default=None,
                     help="median tolerance instead of 1e-4 (below the Delta S' of most nodes the filter acts)")
-    ap.add_argument("--workload", choices=("headline", "elbm", "smooth", "batch"), default="headline",
+    ap.add_argument("--workload", choices=("headline", "elbm", "smooth", "batch") + tuple(SHEAR_STORAGE),
+                    default="headline",
                     help="elbm: entropic f*, ELBM collisions, no limiter; smooth: the headline limiters plus "
                          "the smooth ensemble factor (k = 1/2, delta = 0.01); batch: only the ensemble of 256 "
-                         "cavities (its own JSON line)")
+                         "cavities (its own JSON line); shear-f32/-f16/-bf16: only the 8192^2 double shear "
+                         "layer in that storage (its own JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise kernel over 1 GiB (known bytes) to scale HBM counters")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
@@ -534,6 +544,14 @@ def main():
         res = hopf.run(L, list(np_arange_inclusive(a, b, c)), n=args.hopf_n, time_units=args.hopf_units,
                        stream=stream.cuda_stream)
         print(json.dumps({"hopf": res}), flush=True)
+        return
+    if args.workload in SHEAR_STORAGE:
+        name = SHEAR_STORAGE[args.workload]
+        storage = {"f32": L.LBM_F32, "f16": L.LBM_F16_SHIFT, "bf16": L.LBM_BF16_SHIFT}[name]
+        res = {"shear_8192": {name: shear_run(torch, L, wl, stream, storage, args.steps, args.warmup)}}
+        if args.calibrate_copy:
+            res["copy_calibration"] = copy_calibration(torch, stream)
+        print(json.dumps(res), flush=True)
         return
     if args.workload == "batch":
         res = cavity_batch(torch, L, wl, stream, args.steps, kernel_steps=args.kernel_steps, tile_x=args.tile_x,
